@@ -1,0 +1,51 @@
+// mc_internal.h -- workspace layouts and kernel launchers behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mc.h"
+
+namespace mc {
+
+constexpr int kMaxRowsPerBlock = 16;
+constexpr int64_t kPlainTargetBlocks = 2048;
+
+struct DevState {
+    int status;   // kStatus* of the running factorisation
+    int bad_step; // first step whose pivot row was zero / non-finite
+};
+
+// Device workspace of the plain path (FP64), carved from the caller's
+// buffer.  W holds rows 1..n-1 of the matrix being condensed, row stride
+// ldw (a multiple of 16 doubles = 128 bytes).
+struct PlainWork {
+    double* W;
+    int64_t ldw;
+    double* r[2];    // pivot row / pivot, ping-pong by step parity
+    double* piv_val; // pivot of each step
+    int* piv_slot;   // slot of each step's pivot in its row
+    int* colid;      // original column held by each slot
+    DevState* state;
+};
+
+size_t plain_workspace_bytes(int64_t n);
+PlainWork plain_carve(void* work, int64_t n);
+hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
+                            PlainWork w, mc_result* out, hipStream_t stream);
+
+hipError_t launch_write_result(mc_result* out, double logabsdet, double sign,
+                               int64_t info, hipStream_t stream);
+
+// Optional event timing of the dominant kernel (mc_profile_enable).
+struct ProfMark {
+    int slot = -1;
+};
+ProfMark prof_begin(hipStream_t stream);
+void prof_end(hipStream_t stream, ProfMark m, int64_t launches,
+              double alg_bytes, double alg_flops);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+} // namespace mc
