@@ -93,10 +93,14 @@ size_t mc_logdet_workspace(int64_t n, int dtype, int update, int64_t b);
  * lda     >= max(1, n).
  * dtype   mc_dtype of A.
  * update  mc_update (MC_UPDATE_NATIVE for the plain path).
- * b       panel width: 0 = plain (unblocked) condensation, one step per
+ * b       panel width.  0 = plain (unblocked) condensation, one step per
  *         pivot with the paper's column slot move (Section 2.4, Figure 6);
- *         other widths are rejected with MC_ERR_UNSUPPORTED until the
- *         blocked path is present.
+ *         FP64 storage only.  1..128 = panel-blocked (delayed-update)
+ *         condensation: b steps on a panel of b rows, then one trailing
+ *         update of the rows below on the matrix cores (block condensation,
+ *         Section 2.5 / Future Work).  < 0 = the library's default width.
+ *         Supported: (F64, NATIVE) plain or blocked; (F32, NATIVE | F32 |
+ *         BF16X3) blocked.  Others return MC_ERR_UNSUPPORTED.
  * out     device pointer to one mc_result, written on `stream`.
  * work    device workspace of at least mc_logdet_workspace(...) bytes,
  *         256-byte aligned.  Its contents on entry are ignored.

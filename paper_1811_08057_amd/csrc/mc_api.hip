@@ -117,6 +117,56 @@ PlainWork plain_carve(void* work, int64_t n)
     return w;
 }
 
+// ------------------------------------------------------------- blocked path
+static int64_t blocked_ldw(int64_t n, size_t elem)
+{
+    const int64_t per = 128 / (int64_t)elem; // 128-byte rows
+    return (n + per - 1) / per * per;
+}
+
+size_t blocked_workspace_bytes(int64_t n, int dtype, int64_t b)
+{
+    const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    const int64_t ldw = blocked_ldw(n, elem);
+    size_t t = 0;
+    t += align_up(elem * (size_t)n * (size_t)ldw, kAlign);     // W
+    t += align_up(elem * (size_t)n * (size_t)b, kAlign);       // L
+    t += align_up(sizeof(int) * (size_t)n, kAlign);            // piv_pos
+    t += align_up(sizeof(double) * (size_t)n, kAlign);         // piv_val
+    t += 2 * align_up(sizeof(int) * (size_t)n, kAlign);        // perm, colsrc
+    t += 2 * align_up(sizeof(int) * (size_t)kMaxPanel, kAlign); // srcp, moved
+    t += align_up(sizeof(DevState), kAlign);
+    return t;
+}
+
+template <typename T>
+BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b)
+{
+    const int64_t ldw = blocked_ldw(n, sizeof(T));
+    char* p = static_cast<char*>(work);
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += align_up(bytes, kAlign);
+        return q;
+    };
+    BlkWork<T> w;
+    w.ldw = ldw;
+    w.W = reinterpret_cast<T*>(take(sizeof(T) * (size_t)n * (size_t)ldw));
+    w.ldl = b;
+    w.L = reinterpret_cast<T*>(take(sizeof(T) * (size_t)n * (size_t)b));
+    w.piv_pos = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
+    w.piv_val = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n));
+    w.perm = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
+    w.colsrc = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
+    w.srcp = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
+    w.moved = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
+    w.state = reinterpret_cast<DevState*>(take(sizeof(DevState)));
+    return w;
+}
+
+template BlkWork<double> blocked_carve<double>(void*, int64_t, int64_t);
+template BlkWork<float> blocked_carve<float>(void*, int64_t, int64_t);
+
 } // namespace mc
 
 using namespace mc;
@@ -174,11 +224,32 @@ static bool plain_supported(int dtype, int update, int64_t b)
     return b == 0 && dtype == MC_DTYPE_F64 && update == MC_UPDATE_NATIVE;
 }
 
+// Panel width for b < 0 ("library default").
+static int64_t default_panel(int64_t n, int dtype)
+{
+    (void)dtype;
+    if (n <= 256) return 32;
+    if (n <= 1024) return 64;
+    return 128;
+}
+
+static bool blocked_supported(int dtype, int update, int64_t b)
+{
+    if (b == 0 || b > kMaxPanel) return false;
+    if (dtype == MC_DTYPE_F64) return update == MC_UPDATE_NATIVE;
+    return dtype == MC_DTYPE_F32 &&
+           (update == MC_UPDATE_NATIVE || update == MC_UPDATE_F32 ||
+            update == MC_UPDATE_BF16X3);
+}
+
 extern "C" size_t mc_logdet_workspace(int64_t n, int dtype, int update,
                                       int64_t b)
 {
     if (n < 0 || n > kMaxN) return 0;
     if (plain_supported(dtype, update, b)) return plain_workspace_bytes(n);
+    if (b < 0) b = default_panel(n, dtype);
+    if (blocked_supported(dtype, update, b))
+        return blocked_workspace_bytes(n, dtype, b);
     return 0;
 }
 
@@ -194,16 +265,33 @@ extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
     if (update < MC_UPDATE_NATIVE || update > MC_UPDATE_BF16X3) return -5;
     if (out == nullptr) return -7;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (!plain_supported(dtype, update, b)) return MC_ERR_UNSUPPORTED;
+    if (b < 0) b = default_panel(n, dtype);
+    const bool plain = plain_supported(dtype, update, b);
+    if (!plain && !blocked_supported(dtype, update, b))
+        return MC_ERR_UNSUPPORTED;
     if (n == 0)
         return launch_write_result(out, 0.0, 1.0, 0, st) == hipSuccess
                    ? MC_OK
                    : MC_ERR_HIP;
     if (work == nullptr) return -8;
     if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return -8;
-    if (work_bytes < plain_workspace_bytes(n)) return MC_ERR_WORKSPACE;
-    const PlainWork w = plain_carve(work, n);
-    const hipError_t e = launch_plain_f64(static_cast<const double*>(A), n,
-                                          lda, w, out, st);
+    hipError_t e;
+    if (plain) {
+        if (work_bytes < plain_workspace_bytes(n)) return MC_ERR_WORKSPACE;
+        const PlainWork w = plain_carve(work, n);
+        e = launch_plain_f64(static_cast<const double*>(A), n, lda, w, out, st);
+    } else {
+        if (work_bytes < blocked_workspace_bytes(n, dtype, b))
+            return MC_ERR_WORKSPACE;
+        if (dtype == MC_DTYPE_F64)
+            e = launch_blocked<double>(static_cast<const double*>(A), n, lda,
+                                       b, update,
+                                       blocked_carve<double>(work, n, b), out,
+                                       st);
+        else
+            e = launch_blocked<float>(static_cast<const float*>(A), n, lda, b,
+                                      update, blocked_carve<float>(work, n, b),
+                                      out, st);
+    }
     return e == hipSuccess ? MC_OK : MC_ERR_HIP;
 }

@@ -30,6 +30,35 @@ struct PlainWork {
     DevState* state;
 };
 
+// Device workspace of the blocked path.  W is the matrix being factored in
+// place (row stride ldw); L receives the multipliers of the rows below the
+// current panel; the integer arrays track pivot positions and the column
+// exchanges.
+template <typename T>
+struct BlkWork {
+    T* W;
+    int64_t ldw;
+    T* L;          // (n x b), row stride ldl = b
+    int64_t ldl;
+    int* piv_pos;  // position of each step's pivot in its row (>= step)
+    double* piv_val;
+    int* perm;     // perm[pos] = original column now at position pos
+    int* colsrc;   // source position of each trailing destination position
+    int* srcp;     // source position of each panel column s0 + t
+    int* moved;    // trailing positions remapped by the previous panel
+    DevState* state;
+};
+
+constexpr int64_t kMaxPanel = 128;
+
+size_t blocked_workspace_bytes(int64_t n, int dtype, int64_t b);
+template <typename T>
+BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b);
+template <typename T>
+hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
+                          int update, BlkWork<T> w, mc_result* out,
+                          hipStream_t stream);
+
 size_t plain_workspace_bytes(int64_t n);
 PlainWork plain_carve(void* work, int64_t n);
 hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
