@@ -72,12 +72,17 @@ typedef int mc_status;
 #define MC_ERR_UNSUPPORTED (-102) /* combination not provided            */
 
 #define MC_INFO_NONFINITE (-1)
+#define MC_INFO_BADARG (-3) /* batched: this matrix's n / lda / pointer invalid */
 
 /* Library version as major*10000 + minor*100 + patch. */
 int mc_version(void);
 
 /* Human-readable text for a status code (static storage). */
 const char* mc_status_string(mc_status status);
+
+/* Text of the last HIP error seen by a call on this host thread that
+ * returned MC_ERR_HIP ("no error" if none). */
+const char* mc_last_hip_error(void);
 
 /*
  * Workspace size in bytes for mc_logdet with the same (n, dtype, update, b).
@@ -109,6 +114,101 @@ size_t mc_logdet_workspace(int64_t n, int dtype, int update, int64_t b);
 mc_status mc_logdet(const void* A, int64_t n, int64_t lda, int dtype,
                     int update, int64_t b, mc_result* out, void* work,
                     size_t work_bytes, void* stream);
+
+/*
+ * Factor call: the blocked condensation of mc_logdet run in place, keeping
+ * the factors (the row-k factoring of Section 2.3 with the multipliers of
+ * Figure 6 step 4.8 stored where they were eliminated).  On return A holds
+ * L\U with A_in[:, perm] = L U: row i keeps its multipliers left of i (L),
+ * its pivot at i (diagonal of L) and its factored row right of i (U, unit
+ * diagonal implied); perm[s] is the original column of position s.
+ *
+ * A       device, row-major n x n, row stride lda; overwritten.
+ * b       panel width (1..128) or < 0 for the default; b = 0 is rejected.
+ * perm    device, n int32 (output).
+ * out     device mc_result (as mc_logdet).
+ * work    >= mc_logdet_factor_workspace(n, dtype, update, b) bytes.
+ * After a singular or non-finite result, A and perm are unspecified.
+ */
+size_t mc_logdet_factor_workspace(int64_t n, int dtype, int update,
+                                  int64_t b);
+mc_status mc_logdet_factor(void* A, int64_t n, int64_t lda, int dtype,
+                           int update, int64_t b, int32_t* perm,
+                           mc_result* out, void* work, size_t work_bytes,
+                           void* stream);
+
+/*
+ * Backward call: gradA = g * A^{-T} = g * d log|det A| / dA from the output
+ * of mc_logdet_factor (LU with row stride ld, perm).  A^{-1} = Q U^{-1}
+ * L^{-1}: two blocked triangular substitutions whose off-diagonal updates
+ * run on the matrix cores, then a permuted transpose.
+ *
+ * grad_out  device pointer to one double g (the incoming gradient of
+ *           log|det A|), or NULL for g = 1.
+ * gradA     device, row-major n x n, row stride ldg (output).
+ * work      >= mc_logdet_backward_workspace(n, dtype) bytes.
+ * The factors must come from a call whose result had info == 0.
+ */
+size_t mc_logdet_backward_workspace(int64_t n, int dtype);
+mc_status mc_logdet_backward(const void* LU, int64_t n, int64_t ld,
+                             const int32_t* perm, int dtype,
+                             const double* grad_out, void* gradA, int64_t ldg,
+                             void* work, size_t work_bytes, void* stream);
+
+/*
+ * Batched log-determinants of `batch` independent square matrices of
+ * possibly different sizes (e.g. the covariance matrices of a mixture
+ * model, Abstract), in one persistent kernel launch preceded by a one-block
+ * setup launch; the pair can be captured in a hipGraph.  Each workgroup
+ * takes the largest remaining matrix from a queue and condenses it alone
+ * with the blocked algorithm (largest-|a| pivot per row, row factoring,
+ * trailing updates on the matrix cores).
+ *
+ * A_array    device array of `batch` device pointers (row-major matrices).
+ * n_array    device array of `batch` sizes (int64, 0 <= n_k <= n_max).
+ * lda_array  device array of `batch` row strides (int64, >= max(1, n_k)).
+ * batch      >= 0.
+ * n_max      host value: an upper bound of every n_k; sizes the per-matrix
+ *            workspace regions.  A matrix that breaks n_k <= n_max (or has
+ *            an invalid lda or a NULL pointer) gets {NaN, 0, MC_INFO_BADARG}
+ *            and the others are unaffected.
+ * dtype      MC_DTYPE_F64 (update NATIVE) or MC_DTYPE_F32 (update NATIVE,
+ *            F32 or BF16X3).
+ * b          > 0: this panel width for every matrix (1..128); < 0: the
+ *            per-size table (mc_tune_get / mc_autotune_batched); 0 is
+ *            rejected (the plain path is mc_logdet with b = 0).
+ * out        device array of `batch` mc_result.
+ * work       >= mc_logdet_batched_workspace(batch, n_max, dtype, update, b)
+ *            bytes, 256-byte aligned; after the call it holds each matrix's
+ *            factors in its region (contents otherwise unspecified).
+ */
+size_t mc_logdet_batched_workspace(int64_t batch, int64_t n_max, int dtype,
+                                   int update, int64_t b);
+mc_status mc_logdet_batched(const void* const* A_array, const int64_t* n_array,
+                            const int64_t* lda_array, int64_t batch,
+                            int64_t n_max, int dtype, int update, int64_t b,
+                            mc_result* out, void* work, size_t work_bytes,
+                            void* stream);
+
+/*
+ * The batched path's tuning table: for size buckets n <= 64, 128, 256, 512,
+ * 1024 and larger, a panel width b_k (1..128) and a trailing-update tile
+ * edge tile_k (32 or 64).  One table per (dtype, update), process-wide,
+ * host-side, not thread-safe.  mc_tune_get/mc_tune_set copy 6 entries of
+ * each array (host pointers).
+ *
+ * mc_autotune_batched times candidate (b, tile) pairs per bucket on
+ * synthetic diagonally dominant matrices generated on the device in `work`
+ * (at least mc_autotune_workspace(dtype) bytes), keeps the fastest per
+ * bucket in the table, and synchronises `stream`.  Buckets above
+ * n_max_tune are left unchanged.
+ */
+mc_status mc_tune_get(int dtype, int update, int64_t* b, int* tile);
+mc_status mc_tune_set(int dtype, int update, const int64_t* b,
+                      const int* tile);
+size_t mc_autotune_workspace(int dtype, int64_t n_max_tune);
+mc_status mc_autotune_batched(int dtype, int update, int64_t n_max_tune,
+                              void* work, size_t work_bytes, void* stream);
 
 /*
  * Optional timing of the kernel that dominates a call: the condensation

@@ -31,7 +31,14 @@ _UPDATES = {"native": UPDATE_NATIVE, "f32": UPDATE_F32,
 
 # Every symbol include/mc.h declares (checked by the test suite).
 EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
-           "mc_logdet", "mc_profile_enable", "mc_profile_read")
+           "mc_logdet", "mc_profile_enable", "mc_profile_read",
+           "mc_logdet_batched_workspace", "mc_logdet_batched", "mc_tune_get",
+           "mc_tune_set", "mc_autotune_workspace", "mc_autotune_batched",
+           "mc_last_hip_error", "mc_logdet_factor_workspace",
+           "mc_logdet_factor", "mc_logdet_backward_workspace",
+           "mc_logdet_backward")
+INFO_BADARG = -3
+TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
 
 class MCError(RuntimeError):
@@ -61,6 +68,7 @@ def lib() -> ctypes.CDLL:
     L.mc_version.restype = ctypes.c_int
     L.mc_status_string.argtypes = [ctypes.c_int]
     L.mc_status_string.restype = ctypes.c_char_p
+    L.mc_last_hip_error.restype = ctypes.c_char_p
     L.mc_logdet_workspace.argtypes = [i64, ctypes.c_int, ctypes.c_int, i64]
     L.mc_logdet_workspace.restype = sz
     L.mc_logdet.argtypes = [vp, i64, i64, ctypes.c_int, ctypes.c_int, i64, vp,
@@ -71,6 +79,32 @@ def lib() -> ctypes.CDLL:
     L.mc_profile_enable.restype = ctypes.c_int
     L.mc_profile_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), dp, dp]
     L.mc_profile_read.restype = ctypes.c_int
+    ci = ctypes.c_int
+    L.mc_logdet_batched_workspace.argtypes = [i64, i64, ci, ci, i64]
+    L.mc_logdet_batched_workspace.restype = sz
+    L.mc_logdet_batched.argtypes = [vp, vp, vp, i64, i64, ci, ci, i64, vp, vp,
+                                    sz, vp]
+    L.mc_logdet_batched.restype = ci
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    cip = ctypes.POINTER(ctypes.c_int)
+    L.mc_tune_get.argtypes = [ci, ci, i64p, cip]
+    L.mc_tune_get.restype = ci
+    L.mc_tune_set.argtypes = [ci, ci, i64p, cip]
+    L.mc_tune_set.restype = ci
+    L.mc_autotune_workspace.argtypes = [ci, i64]
+    L.mc_autotune_workspace.restype = sz
+    L.mc_autotune_batched.argtypes = [ci, ci, i64, vp, sz, vp]
+    L.mc_autotune_batched.restype = ci
+    L.mc_logdet_factor_workspace.argtypes = [i64, ci, ci, i64]
+    L.mc_logdet_factor_workspace.restype = sz
+    L.mc_logdet_factor.argtypes = [vp, i64, i64, ci, ci, i64, vp, vp, vp, sz,
+                                   vp]
+    L.mc_logdet_factor.restype = ci
+    L.mc_logdet_backward_workspace.argtypes = [i64, ci]
+    L.mc_logdet_backward_workspace.restype = sz
+    L.mc_logdet_backward.argtypes = [vp, i64, i64, vp, ci, vp, vp, i64, vp, sz,
+                                     vp]
+    L.mc_logdet_backward.restype = ci
     _lib = L
     return L
 
@@ -78,6 +112,8 @@ def lib() -> ctypes.CDLL:
 def _check(status: int, what: str) -> None:
     if status != 0:
         msg = lib().mc_status_string(status).decode()
+        if status == -101:
+            msg += ": " + lib().mc_last_hip_error().decode()
         raise MCError(f"{what}: status {status} ({msg})")
 
 
@@ -179,3 +215,190 @@ def profile_read() -> Profile:
                                  ctypes.byref(by), ctypes.byref(fl)),
            "mc_profile_read")
     return Profile(ms.value, la.value, by.value, fl.value)
+
+
+# ------------------------------------------------------------------ batched
+
+def _dtype_of(t) -> int:
+    return DTYPE_F64 if t == torch.float64 else DTYPE_F32
+
+
+class BatchedPlan:
+    """Device-side description of a batch (pointer, size and stride arrays,
+    workspace, results) for mc_logdet_batched.  The matrices must stay alive
+    and in place while the plan is used.  ``run()`` enqueues the call on the
+    current stream; ``capture()`` records it into a hipGraph (through
+    torch.cuda.CUDAGraph) that ``replay()`` launches."""
+
+    def __init__(self, mats, b: int = -1, update="native"):
+        if not mats:
+            raise ValueError("empty batch")
+        dev = mats[0].device
+        dt = mats[0].dtype
+        for m in mats:
+            if m.dtype != dt or m.device != dev:
+                raise ValueError("all matrices need one dtype and device")
+            _square_rows(m)
+        self.mats = list(mats)
+        self.device = dev
+        self.dtype = dt
+        self.b = b
+        self.update = _update_code(update)
+        self.batch = len(mats)
+        self.n_max = max(m.shape[0] for m in mats)
+        ptrs = [m.data_ptr() for m in mats]
+        ns = [m.shape[0] for m in mats]
+        ldas = [_square_rows(m) for m in mats]
+        self.ptrs = torch.tensor(ptrs, dtype=torch.int64, device=dev)
+        self.ns = torch.tensor(ns, dtype=torch.int64, device=dev)
+        self.ldas = torch.tensor(ldas, dtype=torch.int64, device=dev)
+        nb = lib().mc_logdet_batched_workspace(self.batch, self.n_max,
+                                               _dtype_of(dt), self.update, b)
+        if nb == 0:
+            raise MCError("unsupported combination for the batched path")
+        self.work = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.result = new_result(dev, self.batch)
+        self.graph = None
+
+    def run(self, stream: Optional[torch.cuda.Stream] = None) -> None:
+        st = lib().mc_logdet_batched(
+            self.ptrs.data_ptr(), self.ns.data_ptr(), self.ldas.data_ptr(),
+            self.batch, self.n_max, _dtype_of(self.dtype), self.update, self.b,
+            self.result.data_ptr(), self.work.data_ptr(), self.work.numel(),
+            _stream_ptr(stream, self.device))
+        _check(st, "mc_logdet_batched")
+
+    def capture(self) -> None:
+        self.run()  # warm-up outside the capture (kernel attributes)
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+
+    def replay(self) -> None:
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def results(self) -> list:
+        return read_result(self.result)
+
+
+def logdet_batched(mats, b: int = -1, update="native") -> list:
+    """(sign, log|det|, info) of every matrix of a batch (synchronises)."""
+    plan = BatchedPlan(mats, b=b, update=update)
+    plan.run()
+    return plan.results()
+
+
+def tune_get(dtype=torch.float64, update="native"):
+    b = (ctypes.c_int64 * 6)()
+    t = (ctypes.c_int * 6)()
+    _check(lib().mc_tune_get(_dtype_of(dtype), _update_code(update), b, t),
+           "mc_tune_get")
+    return list(b), list(t)
+
+
+def tune_set(b_list, tile_list, dtype=torch.float64, update="native"):
+    b = (ctypes.c_int64 * 6)(*b_list)
+    t = (ctypes.c_int * 6)(*tile_list)
+    _check(lib().mc_tune_set(_dtype_of(dtype), _update_code(update), b, t),
+           "mc_tune_set")
+
+
+def autotune_batched(dtype=torch.float64, update="native", n_max: int = 1024,
+                     device=None):
+    """Run the library's autotuner for the batched path; returns the table."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    nb = lib().mc_autotune_workspace(_dtype_of(dtype), n_max)
+    if nb == 0:
+        raise MCError("unsupported autotune request")
+    work = torch.empty(nb, dtype=torch.uint8, device=device)
+    _check(lib().mc_autotune_batched(_dtype_of(dtype), _update_code(update),
+                                     n_max, work.data_ptr(), work.numel(),
+                                     _stream_ptr(None, device)),
+           "mc_autotune_batched")
+    del work
+    return tune_get(dtype, update)
+
+
+# ------------------------------------------------------- factor / backward
+
+def factor(a: torch.Tensor, b: int = -1, update="native"):
+    """Factor a copy of `a` in place: returns (lu, perm, result) where
+    a[:, perm] = L U (L\\U stored in lu) and result is the device mc_result
+    buffer (not yet synchronised)."""
+    n = a.shape[0]
+    lu = a.detach().contiguous().clone()
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=a.device)
+    res = new_result(a.device)
+    nb = lib().mc_logdet_factor_workspace(n, _dtype_code(a), _update_code(update),
+                                          b)
+    if nb == 0:
+        raise MCError("unsupported combination for the factor call")
+    work = torch.empty(nb, dtype=torch.uint8, device=a.device)
+    st = lib().mc_logdet_factor(lu.data_ptr(), n, max(n, 1), _dtype_code(a),
+                                _update_code(update), b, perm.data_ptr(),
+                                res.data_ptr(), work.data_ptr(), work.numel(),
+                                _stream_ptr(None, a.device))
+    _check(st, "mc_logdet_factor")
+    return lu, perm[:n], res
+
+
+def backward(lu: torch.Tensor, perm: torch.Tensor,
+             grad_out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g * A^{-T} from factor()'s output; grad_out: device float64 scalar."""
+    n = lu.shape[0]
+    grad = torch.empty_like(lu)
+    nb = lib().mc_logdet_backward_workspace(n, _dtype_code(lu))
+    work = torch.empty(max(nb, 1), dtype=torch.uint8, device=lu.device)
+    g_ptr = None
+    if grad_out is not None:
+        grad_out = grad_out.detach().to(lu.device, torch.float64).contiguous()
+        g_ptr = grad_out.data_ptr()
+    st = lib().mc_logdet_backward(lu.data_ptr(), n, max(n, 1), perm.data_ptr(),
+                                  _dtype_code(lu), g_ptr, grad.data_ptr(),
+                                  max(n, 1), work.data_ptr(), work.numel(),
+                                  _stream_ptr(None, lu.device))
+    _check(st, "mc_logdet_backward")
+    return grad
+
+
+class MCLogDet(torch.autograd.Function):
+    """(sign, log|det A|) with d log|det A| / dA = A^{-T}.
+
+    forward keeps the factors (L\\U and perm) when they fit `mem_budget`
+    bytes (None = always); otherwise backward recomputes them from A."""
+
+    @staticmethod
+    def forward(ctx, a, b=-1, update="native", mem_budget=None):
+        lu, perm, res = factor(a, b=b, update=update)
+        keep = mem_budget is None or lu.numel() * lu.element_size() <= mem_budget
+        if keep:
+            ctx.save_for_backward(lu, perm)
+        else:
+            del lu, perm
+            ctx.save_for_backward(a.detach())
+        ctx.keep = keep
+        ctx.b, ctx.update = b, update
+        sign = res[0, 1].clone()
+        logabs = res[0, 0].clone()
+        ctx.mark_non_differentiable(sign)
+        return sign, logabs
+
+    @staticmethod
+    def backward(ctx, gsign, glogabs):
+        if ctx.keep:
+            lu, perm = ctx.saved_tensors
+        else:
+            (a,) = ctx.saved_tensors
+            lu, perm, _ = factor(a, b=ctx.b, update=ctx.update)
+        g = backward(lu, perm, glogabs)
+        return g, None, None, None
+
+
+def slogdet_autograd(a: torch.Tensor, b: int = -1, update="native",
+                     mem_budget: Optional[int] = None):
+    """Differentiable (sign, log|det A|) as device tensors (no host sync)."""
+    return MCLogDet.apply(a, b, update, mem_budget)

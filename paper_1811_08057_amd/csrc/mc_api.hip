@@ -4,9 +4,11 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <vector>
 
 #include "mc.h"
+#include "mc_batched.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -31,6 +33,15 @@ hipError_t launch_write_result(mc_result* out, double logabsdet, double sign,
     hipLaunchKernelGGL(write_result_kernel, dim3(1), dim3(1), 0, stream, out,
                        logabsdet, sign, info);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ last error
+static thread_local hipError_t g_last_hip = hipSuccess;
+
+hipError_t note_hip_error(hipError_t e)
+{
+    if (e != hipSuccess) g_last_hip = e;
+    return e;
 }
 
 // ------------------------------------------------------------- profiling
@@ -124,23 +135,29 @@ static int64_t blocked_ldw(int64_t n, size_t elem)
     return (n + per - 1) / per * per;
 }
 
-size_t blocked_workspace_bytes(int64_t n, int dtype, int64_t b)
+static size_t blocked_bytes(int64_t n, int dtype, int64_t b, bool with_w)
 {
     const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
     const int64_t ldw = blocked_ldw(n, elem);
     size_t t = 0;
-    t += align_up(elem * (size_t)n * (size_t)ldw, kAlign);     // W
+    if (with_w) t += align_up(elem * (size_t)n * (size_t)ldw, kAlign); // W
     t += align_up(elem * (size_t)n * (size_t)b, kAlign);       // L
     t += align_up(sizeof(int) * (size_t)n, kAlign);            // piv_pos
     t += align_up(sizeof(double) * (size_t)n, kAlign);         // piv_val
     t += 2 * align_up(sizeof(int) * (size_t)n, kAlign);        // perm, colsrc
     t += 2 * align_up(sizeof(int) * (size_t)kMaxPanel, kAlign); // srcp, moved
+    t += align_up(elem * (size_t)kMaxPanel * 16, kAlign);       // dinv
     t += align_up(sizeof(DevState), kAlign);
     return t;
 }
 
+size_t blocked_workspace_bytes(int64_t n, int dtype, int64_t b)
+{
+    return blocked_bytes(n, dtype, b, true);
+}
+
 template <typename T>
-BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b)
+BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b, bool with_w)
 {
     const int64_t ldw = blocked_ldw(n, sizeof(T));
     char* p = static_cast<char*>(work);
@@ -151,7 +168,8 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b)
     };
     BlkWork<T> w;
     w.ldw = ldw;
-    w.W = reinterpret_cast<T*>(take(sizeof(T) * (size_t)n * (size_t)ldw));
+    w.W = with_w ? reinterpret_cast<T*>(take(sizeof(T) * (size_t)n * (size_t)ldw))
+                 : nullptr;
     w.ldl = b;
     w.L = reinterpret_cast<T*>(take(sizeof(T) * (size_t)n * (size_t)b));
     w.piv_pos = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
@@ -160,12 +178,13 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b)
     w.colsrc = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
     w.srcp = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.moved = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
+    w.dinv = reinterpret_cast<T*>(take(sizeof(T) * (size_t)kMaxPanel * 16));
     w.state = reinterpret_cast<DevState*>(take(sizeof(DevState)));
     return w;
 }
 
-template BlkWork<double> blocked_carve<double>(void*, int64_t, int64_t);
-template BlkWork<float> blocked_carve<float>(void*, int64_t, int64_t);
+template BlkWork<double> blocked_carve<double>(void*, int64_t, int64_t, bool);
+template BlkWork<float> blocked_carve<float>(void*, int64_t, int64_t, bool);
 
 } // namespace mc
 
@@ -187,6 +206,11 @@ extern "C" const char* mc_status_string(mc_status status)
     }
     if (status < 0 && status > -20) return "invalid argument";
     return "unknown status";
+}
+
+extern "C" const char* mc_last_hip_error(void)
+{
+    return hipGetErrorString(g_last_hip);
 }
 
 extern "C" mc_status mc_profile_enable(int on)
@@ -253,6 +277,416 @@ extern "C" size_t mc_logdet_workspace(int64_t n, int dtype, int update,
     return 0;
 }
 
+// ------------------------------------------------------------- batched path
+
+static TuneTable default_table(int dtype)
+{
+    TuneTable t;
+    const int64_t b64[kTuneBuckets] = {16, 32, 32, 64, 64, 64};
+    const int64_t b32[kTuneBuckets] = {16, 32, 64, 64, 64, 64};
+    const int tile[kTuneBuckets] = {32, 32, 64, 64, 64, 64};
+    for (int k = 0; k < kTuneBuckets; ++k) {
+        t.b[k] = dtype == MC_DTYPE_F64 ? b64[k] : b32[k];
+        t.tile[k] = tile[k];
+    }
+    return t;
+}
+
+static bool g_tune_init = false;
+static TuneTable g_tune[2][3]; // [dtype][update]
+
+static TuneTable& tune_table(int dtype, int update)
+{
+    if (!g_tune_init) {
+        for (int d = 0; d < 2; ++d)
+            for (int u = 0; u < 3; ++u) g_tune[d][u] = default_table(d);
+        g_tune_init = true;
+    }
+    return g_tune[dtype][update];
+}
+
+static bool batched_supported(int dtype, int update)
+{
+    if (dtype == MC_DTYPE_F64) return update == MC_UPDATE_NATIVE;
+    return dtype == MC_DTYPE_F32 &&
+           (update == MC_UPDATE_NATIVE || update == MC_UPDATE_F32 ||
+            update == MC_UPDATE_BF16X3);
+}
+
+static TuneTable effective_table(int dtype, int update, int64_t b)
+{
+    TuneTable t = tune_table(dtype, update);
+    if (b > 0)
+        for (int k = 0; k < kTuneBuckets; ++k) t.b[k] = b;
+    return t;
+}
+
+static size_t batched_header_bytes(int64_t batch)
+{
+    return align_up(sizeof(int) * 64, 256) + align_up(sizeof(int) * (size_t)std::max<int64_t>(batch, 1), 256);
+}
+
+extern "C" size_t mc_logdet_batched_workspace(int64_t batch, int64_t n_max,
+                                              int dtype, int update, int64_t b)
+{
+    if (batch < 0 || n_max < 0 || n_max > kMaxN || b == 0 || b > kMaxPanel)
+        return 0;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return 0;
+    if (update < 0 || update > 2 || !batched_supported(dtype, update)) return 0;
+    const TuneTable t = effective_table(dtype, update, b);
+    return batched_header_bytes(batch) +
+           (size_t)batch * batched_region_bytes(n_max, dtype, t);
+}
+
+static mc_status batched_call(const void* const* A_array, const int64_t* n_array,
+                              const int64_t* lda_array, int64_t batch,
+                              int64_t n_max, int dtype, int update,
+                              const TuneTable& t, mc_result* out, void* work,
+                              size_t work_bytes, hipStream_t st)
+{
+    const size_t need = batched_header_bytes(batch) +
+                        (size_t)batch * batched_region_bytes(n_max, dtype, t);
+    if (work_bytes < need) return MC_ERR_WORKSPACE;
+    BatchArgs a;
+    a.A_array = A_array;
+    a.n_array = n_array;
+    a.lda_array = lda_array;
+    a.batch = batch;
+    a.n_max = n_max;
+    a.update = update;
+    a.table = t;
+    unsigned char* base = static_cast<unsigned char*>(work);
+    a.counter = reinterpret_cast<int*>(base);
+    a.order = reinterpret_cast<int*>(base + align_up(sizeof(int) * 64, 256));
+    a.regions = base + batched_header_bytes(batch);
+    a.region_stride = batched_region_bytes(n_max, dtype, t);
+    a.out = out;
+    const hipError_t e = launch_batched(a, dtype, batched_lds_bytes(dtype, t), st);
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
+}
+
+extern "C" mc_status mc_logdet_batched(const void* const* A_array,
+                                       const int64_t* n_array,
+                                       const int64_t* lda_array, int64_t batch,
+                                       int64_t n_max, int dtype, int update,
+                                       int64_t b, mc_result* out, void* work,
+                                       size_t work_bytes, void* stream)
+{
+    if (batch < 0) return -4;
+    if (batch > 0 && (A_array == nullptr)) return -1;
+    if (batch > 0 && (n_array == nullptr)) return -2;
+    if (batch > 0 && (lda_array == nullptr)) return -3;
+    if (n_max < 0 || n_max > kMaxN) return -5;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -6;
+    if (update < MC_UPDATE_NATIVE || update > MC_UPDATE_BF16X3) return -7;
+    if (b == 0 || b > kMaxPanel) return -8;
+    if (!batched_supported(dtype, update)) return MC_ERR_UNSUPPORTED;
+    if (batch > 0 && out == nullptr) return -9;
+    if (batch == 0) return MC_OK;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -10;
+    return batched_call(A_array, n_array, lda_array, batch, n_max, dtype,
+                        update, effective_table(dtype, update, b), out, work,
+                        work_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mc_status mc_tune_get(int dtype, int update, int64_t* b, int* tile)
+{
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -1;
+    if (update < 0 || update > 2) return -2;
+    const TuneTable& t = tune_table(dtype, update);
+    for (int k = 0; k < kTuneBuckets; ++k) {
+        if (b) b[k] = t.b[k];
+        if (tile) tile[k] = t.tile[k];
+    }
+    return MC_OK;
+}
+
+extern "C" mc_status mc_tune_set(int dtype, int update, const int64_t* b,
+                                 const int* tile)
+{
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -1;
+    if (update < 0 || update > 2) return -2;
+    if (!b) return -3;
+    if (!tile) return -4;
+    for (int k = 0; k < kTuneBuckets; ++k) {
+        if (b[k] < 1 || b[k] > kMaxPanel) return -3;
+        if (tile[k] != 32 && tile[k] != 64) return -4;
+    }
+    TuneTable& t = tune_table(dtype, update);
+    for (int k = 0; k < kTuneBuckets; ++k) {
+        t.b[k] = b[k];
+        t.tile[k] = tile[k];
+    }
+    return MC_OK;
+}
+
+// --- autotuner: synthetic batches per bucket, candidates timed with events
+namespace {
+
+constexpr int kTuneReps = 2;
+constexpr int64_t kTuneCandB[] = {16, 32, 64, 128};
+constexpr int kTuneCandTile[] = {32, 64};
+
+int64_t tune_size(int k, int64_t n_max_tune)
+{
+    if (k < kTuneBuckets - 1) return std::min<int64_t>(tune_bucket_max(k), n_max_tune);
+    return n_max_tune > tune_bucket_max(kTuneBuckets - 2) ? n_max_tune : 0;
+}
+
+int64_t tune_count(int64_t n, int elem)
+{
+    const double bytes = (double)elem * n * n;
+    const int64_t cap = (int64_t)(1.0e9 / std::max(bytes, 1.0));
+    return std::max<int64_t>(8, std::min<int64_t>(512, cap));
+}
+
+template <typename T>
+__global__ void tune_fill(T* A, int64_t n, int64_t count, uint32_t seed)
+{
+    const int64_t total = n * n * count;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = e / (n * n), r = e % (n * n), i = r / n, j = r % n;
+        uint32_t h = (uint32_t)(e * 2654435761u) ^ seed;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        const double u = (double)(h & 0xffffff) / 16777216.0 * 2.0 - 1.0;
+        A[e] = (T)(u + (i == j ? (double)n : 0.0));
+        (void)m;
+    }
+}
+
+__global__ void tune_meta(const unsigned char* base, size_t elem, int64_t n,
+                          int64_t count, const void** ptrs, int64_t* ns,
+                          int64_t* ldas)
+{
+    for (int64_t k = threadIdx.x; k < count; k += blockDim.x) {
+        ptrs[k] = base + (size_t)k * n * n * elem;
+        ns[k] = n;
+        ldas[k] = n;
+    }
+}
+
+size_t tune_bytes(int dtype, int64_t n, const TuneTable& worst)
+{
+    const int elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    const int64_t count = tune_count(n, elem);
+    size_t t = align_up((size_t)elem * n * n * count, 256);
+    t += 3 * align_up(sizeof(int64_t) * count, 256);
+    t += align_up(sizeof(mc_result) * count, 256);
+    t += batched_header_bytes(count) + (size_t)count * batched_region_bytes(n, dtype, worst);
+    return t;
+}
+
+TuneTable worst_table()
+{
+    TuneTable t;
+    for (int k = 0; k < kTuneBuckets; ++k) {
+        t.b[k] = kMaxPanel;
+        t.tile[k] = 64;
+    }
+    return t;
+}
+
+} // namespace
+
+extern "C" size_t mc_autotune_workspace(int dtype, int64_t n_max_tune)
+{
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return 0;
+    if (n_max_tune < 1 || n_max_tune > 4096) return 0;
+    size_t best = 0;
+    for (int k = 0; k < kTuneBuckets; ++k) {
+        const int64_t n = tune_size(k, n_max_tune);
+        if (n > 0) best = std::max(best, tune_bytes(dtype, n, worst_table()));
+    }
+    return best;
+}
+
+extern "C" mc_status mc_autotune_batched(int dtype, int update,
+                                         int64_t n_max_tune, void* work,
+                                         size_t work_bytes, void* stream)
+{
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -1;
+    if (update < 0 || update > 2) return -2;
+    if (!batched_supported(dtype, update)) return MC_ERR_UNSUPPORTED;
+    if (n_max_tune < 1 || n_max_tune > 4096) return -3;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -4;
+    if (work_bytes < mc_autotune_workspace(dtype, n_max_tune)) return MC_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    TuneTable& table = tune_table(dtype, update);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MC_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MC_ERR_HIP;
+    }
+    mc_status rc = MC_OK;
+    for (int k = 0; k < kTuneBuckets && rc == MC_OK; ++k) {
+        const int64_t n = tune_size(k, n_max_tune);
+        if (n <= 0) continue;
+        const int64_t count = tune_count(n, elem);
+        unsigned char* p = static_cast<unsigned char*>(work);
+        unsigned char* mats = p;
+        p += align_up((size_t)elem * n * n * count, 256);
+        const void** ptrs = reinterpret_cast<const void**>(p);
+        p += align_up(sizeof(int64_t) * count, 256);
+        int64_t* ns = reinterpret_cast<int64_t*>(p);
+        p += align_up(sizeof(int64_t) * count, 256);
+        int64_t* ldas = reinterpret_cast<int64_t*>(p);
+        p += align_up(sizeof(int64_t) * count, 256);
+        mc_result* outs = reinterpret_cast<mc_result*>(p);
+        p += align_up(sizeof(mc_result) * count, 256);
+        const size_t rest = work_bytes - (size_t)(p - static_cast<unsigned char*>(work));
+        if (dtype == MC_DTYPE_F64)
+            hipLaunchKernelGGL(tune_fill<double>, dim3(1024), dim3(256), 0, st,
+                               reinterpret_cast<double*>(mats), n, count, 12345u + k);
+        else
+            hipLaunchKernelGGL(tune_fill<float>, dim3(1024), dim3(256), 0, st,
+                               reinterpret_cast<float*>(mats), n, count, 12345u + k);
+        hipLaunchKernelGGL(tune_meta, dim3(1), dim3(256), 0, st, mats, (size_t)elem, n,
+                           count, ptrs, ns, ldas);
+        float best_ms = 1e30f;
+        int64_t best_b = table.b[k];
+        int best_tile = table.tile[k];
+        for (int64_t cb : kTuneCandB) {
+            if (cb > n && cb != kTuneCandB[0]) continue;
+            for (int ct : kTuneCandTile) {
+                TuneTable t = table;
+                t.b[k] = cb;
+                t.tile[k] = ct;
+                mc_status s1 = batched_call(ptrs, ns, ldas, count, n, dtype, update, t,
+                                            outs, p, rest, st);
+                if (s1 != MC_OK) { rc = s1; break; }
+                if (hipEventRecord(e0, st) != hipSuccess) { rc = MC_ERR_HIP; break; }
+                for (int r = 0; r < kTuneReps && rc == MC_OK; ++r)
+                    rc = batched_call(ptrs, ns, ldas, count, n, dtype, update, t, outs,
+                                      p, rest, st);
+                if (rc != MC_OK) break;
+                if (hipEventRecord(e1, st) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess) { rc = MC_ERR_HIP; break; }
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = MC_ERR_HIP; break; }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_b = cb;
+                    best_tile = ct;
+                }
+            }
+            if (rc != MC_OK) break;
+        }
+        if (rc == MC_OK) {
+            table.b[k] = best_b;
+            table.tile[k] = best_tile;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+// ------------------------------------------------------ factor / backward
+
+extern "C" size_t mc_logdet_factor_workspace(int64_t n, int dtype, int update,
+                                             int64_t b)
+{
+    if (n < 0 || n > kMaxN) return 0;
+    if (b < 0) b = default_panel(n, dtype);
+    if (!blocked_supported(dtype, update, b)) return 0;
+    return blocked_bytes(n, dtype, b, false);
+}
+
+extern "C" mc_status mc_logdet_factor(void* A, int64_t n, int64_t lda,
+                                      int dtype, int update, int64_t b,
+                                      int32_t* perm, mc_result* out,
+                                      void* work, size_t work_bytes,
+                                      void* stream)
+{
+    if (n < 0 || n > kMaxN) return -2;
+    if (n > 0 && A == nullptr) return -1;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -4;
+    if (update < MC_UPDATE_NATIVE || update > MC_UPDATE_BF16X3) return -5;
+    if (b < 0) b = default_panel(n, dtype);
+    if (!blocked_supported(dtype, update, b)) return MC_ERR_UNSUPPORTED;
+    if (n > 0 && perm == nullptr) return -7;
+    if (out == nullptr) return -8;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0)
+        return launch_write_result(out, 0.0, 1.0, 0, st) == hipSuccess ? MC_OK
+                                                                       : MC_ERR_HIP;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -9;
+    if (work_bytes < blocked_bytes(n, dtype, b, false)) return MC_ERR_WORKSPACE;
+    hipError_t e;
+    if (dtype == MC_DTYPE_F64) {
+        BlkWork<double> w = blocked_carve<double>(work, n, b, false);
+        w.W = static_cast<double*>(A);
+        w.ldw = lda;
+        w.perm = perm;
+        e = launch_blocked<double>(w.W, n, lda, b, update, w, out, st, true);
+    } else {
+        BlkWork<float> w = blocked_carve<float>(work, n, b, false);
+        w.W = static_cast<float*>(A);
+        w.ldw = lda;
+        w.perm = perm;
+        e = launch_blocked<float>(w.W, n, lda, b, update, w, out, st, true);
+    }
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
+}
+
+extern "C" size_t mc_logdet_backward_workspace(int64_t n, int dtype)
+{
+    if (n < 0 || n > kMaxN) return 0;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return 0;
+    const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    const int64_t ldz = blocked_ldw(n, elem);
+    return align_up(elem * (size_t)n * (size_t)ldz, kAlign) +
+           align_up(sizeof(int) * (size_t)std::max<int64_t>(n, 1), kAlign) +
+           align_up(sizeof(DevState), kAlign);
+}
+
+extern "C" mc_status mc_logdet_backward(const void* LU, int64_t n, int64_t ld,
+                                        const int32_t* perm, int dtype,
+                                        const double* grad_out, void* gradA,
+                                        int64_t ldg, void* work,
+                                        size_t work_bytes, void* stream)
+{
+    if (n < 0 || n > kMaxN) return -2;
+    if (n > 0 && LU == nullptr) return -1;
+    if (ld < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && perm == nullptr) return -4;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -5;
+    if (n > 0 && gradA == nullptr) return -7;
+    if (ldg < (n > 1 ? n : 1)) return -8;
+    if (n == 0) return MC_OK;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -9;
+    if (work_bytes < mc_logdet_backward_workspace(n, dtype)) return MC_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    const int64_t ldz = blocked_ldw(n, elem);
+    char* p = static_cast<char*>(work);
+    void* Z = p;
+    p += align_up(elem * (size_t)n * (size_t)ldz, kAlign);
+    int* ident = reinterpret_cast<int*>(p);
+    p += align_up(sizeof(int) * (size_t)n, kAlign);
+    DevState* state = reinterpret_cast<DevState*>(p);
+    hipError_t e;
+    if (dtype == MC_DTYPE_F64)
+        e = launch_backward<double>(static_cast<const double*>(LU), ld, perm, n,
+                                    grad_out, static_cast<double*>(gradA), ldg,
+                                    BwdWork<double>{static_cast<double*>(Z), ldz,
+                                                    ident, state},
+                                    st);
+    else
+        e = launch_backward<float>(static_cast<const float*>(LU), ld, perm, n,
+                                   grad_out, static_cast<float*>(gradA), ldg,
+                                   BwdWork<float>{static_cast<float*>(Z), ldz,
+                                                  ident, state},
+                                   st);
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
+}
+
 extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
                                int dtype, int update, int64_t b,
                                mc_result* out, void* work, size_t work_bytes,
@@ -293,5 +727,5 @@ extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
                                       update, blocked_carve<float>(work, n, b),
                                       out, st);
     }
-    return e == hipSuccess ? MC_OK : MC_ERR_HIP;
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }

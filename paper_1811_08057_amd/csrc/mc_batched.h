@@ -1,0 +1,46 @@
+// mc_batched.h -- the batched path's arguments and tuning table.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mc.h"
+#include "mc_internal.h"
+
+namespace mc {
+
+// Size buckets of the tuning table: n <= 64, 128, 256, 512, 1024, larger.
+constexpr int kTuneBuckets = 6;
+
+__host__ __device__ inline int64_t tune_bucket_max(int k)
+{
+    return k >= kTuneBuckets - 1 ? INT64_MAX : ((int64_t)64 << k);
+}
+
+struct TuneTable {
+    int64_t b[kTuneBuckets]; // panel width per bucket
+    int tile[kTuneBuckets];  // trailing-update tile edge (32 or 64)
+};
+
+struct BatchArgs {
+    const void* const* A_array; // device array of device pointers
+    const int64_t* n_array;     // device
+    const int64_t* lda_array;   // device
+    int64_t batch;
+    int64_t n_max;
+    int update;
+    TuneTable table;
+    unsigned char* regions; // batch regions of region_stride bytes
+    size_t region_stride;
+    int* counter; // queue head
+    int* order;   // matrices by decreasing size
+    mc_result* out;
+};
+
+size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t);
+size_t batched_lds_bytes(int dtype, const TuneTable& t);
+hipError_t launch_batched(const BatchArgs& a, int dtype, size_t lds_bytes,
+                          hipStream_t stream);
+
+} // namespace mc

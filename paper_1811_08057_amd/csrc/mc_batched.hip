@@ -1,0 +1,700 @@
+// mc_batched.hip -- many matrices of uneven sizes in one persistent launch.
+//
+// Use case: the log-determinants of many covariance matrices, e.g. the
+// components of a mixture model (Abstract).  Each workgroup repeatedly takes
+// the next matrix from an atomic queue ordered largest first and condenses
+// it alone: the blocked algorithm of mc_blocked.hip (panel steps with the
+// largest-|a| pivot and row factoring, gathered triangular solve, trailing
+// update on the matrix cores) expressed at workgroup level, with the
+// matrix in its own region of the workspace.  A setup kernel resets the
+// queue and orders the batch; the two kernels are the whole call, so a
+// caller can capture it in a hipGraph.
+//
+// Panel width b and the trailing-update tile come from a small table keyed
+// by size bucket (filled by mc_autotune_batched, or defaults).
+#include <algorithm>
+
+#include "mc_batched.h"
+#include "mc_device.h"
+#include "mc_mfma.h"
+
+namespace mc {
+
+constexpr int kBT = 256; // threads per workgroup (4 wavefronts)
+
+__host__ __device__ inline int bucket_of(int64_t n)
+{
+    int k = 0;
+    while (k < kTuneBuckets - 1 && n > tune_bucket_max(k)) ++k;
+    return k;
+}
+
+__host__ __device__ inline int64_t bat_ldw(int64_t n, int elem)
+{
+    const int64_t per = 128 / elem;
+    return (n + per - 1) / per * per;
+}
+
+__host__ __device__ inline size_t bat_align(size_t x) { return (x + 255) / 256 * 256; }
+
+// Bytes of one matrix's region for size n and panel width b.
+__host__ __device__ inline size_t bat_region_bytes(int64_t n, int64_t b, int elem)
+{
+    const size_t nblk = (size_t)((b + 15) / 16);
+    size_t t = 0;
+    t += bat_align((size_t)elem * (size_t)n * (size_t)bat_ldw(n, elem)); // W
+    t += bat_align((size_t)elem * (size_t)n * (size_t)b);               // L
+    t += 3 * bat_align(sizeof(int) * (size_t)n);   // piv_pos, perm, colsrc
+    t += bat_align(sizeof(double) * (size_t)n);    // piv_val
+    t += bat_align(sizeof(int) * (size_t)b);       // srcp
+    t += bat_align((size_t)elem * nblk * 256);     // dinv
+    return t;
+}
+
+template <typename T>
+struct Region {
+    T* W;
+    int64_t ldw;
+    T* L;
+    int* piv_pos;
+    int* perm;
+    int* colsrc;
+    double* piv_val;
+    int* srcp;
+    T* dinv;
+};
+
+template <typename T>
+__device__ inline Region<T> carve_region(unsigned char* base, int64_t n,
+                                         int64_t b)
+{
+    Region<T> r;
+    const int elem = (int)sizeof(T);
+    r.ldw = bat_ldw(n, elem);
+    unsigned char* p = base;
+    auto take = [&](size_t bytes) {
+        unsigned char* q = p;
+        p += bat_align(bytes);
+        return q;
+    };
+    r.W = reinterpret_cast<T*>(take((size_t)elem * n * r.ldw));
+    r.L = reinterpret_cast<T*>(take((size_t)elem * n * b));
+    r.piv_pos = reinterpret_cast<int*>(take(sizeof(int) * n));
+    r.perm = reinterpret_cast<int*>(take(sizeof(int) * n));
+    r.colsrc = reinterpret_cast<int*>(take(sizeof(int) * n));
+    r.piv_val = reinterpret_cast<double*>(take(sizeof(double) * n));
+    r.srcp = reinterpret_cast<int*>(take(sizeof(int) * b));
+    r.dinv = reinterpret_cast<T*>(take((size_t)elem * ((b + 15) / 16) * 256));
+    return r;
+}
+
+// ------------------------------------------------------------------ setup
+
+// One block: reset the queue and rank the matrices by size, largest first
+// (ties by index), so big matrices start early and small ones fill in.
+// (Batches larger than kSortMax keep their given order.)
+constexpr int64_t kSortMax = 16384;
+
+__global__ void __launch_bounds__(kBT)
+batched_setup(const int64_t* __restrict__ n_array, int64_t batch, int* counter,
+              int* order)
+{
+    if (threadIdx.x == 0) *counter = 0;
+    if (batch > kSortMax) {
+        for (int64_t i = threadIdx.x; i < batch; i += kBT) order[i] = (int)i;
+        return;
+    }
+    for (int64_t i = threadIdx.x; i < batch; i += kBT) {
+        const int64_t ni = n_array[i];
+        int64_t rank = 0;
+        for (int64_t j = 0; j < batch; ++j) {
+            const int64_t nj = n_array[j];
+            rank += (nj > ni || (nj == ni && j < i)) ? 1 : 0;
+        }
+        order[rank] = (int)i;
+    }
+}
+
+// --------------------------------------------------------- workgroup stages
+
+struct WgShared {
+    PivotKey keys[kBT / kWave];
+    int flag;
+    int status;
+    int piv_slot;
+    int qidx;
+    double piv;
+    double vs;
+    double csum[kBT];
+    double ccomp[kBT];
+    int cpar[kBT];
+};
+
+// Argmax of row s over positions [s, n), record the pivot, factor the row
+// (position s <- p, position l <- old(s)/p, others /p).  Returns the status.
+template <typename T>
+__device__ int wg_pivot_row(Region<T>& r, int64_t n, int64_t s, WgShared& sh)
+{
+    const int tid = threadIdx.x;
+    T* row = r.W + s * r.ldw;
+    PivotKey k = no_candidate();
+    bool bad = false;
+    for (int64_t j = s + tid; j < n; j += kBT) {
+        const T v = row[j];
+        if (j == s) sh.vs = (double)v;
+        if (!offer(k, (double)v, r.perm[j], (int)j)) bad = true;
+    }
+    k = block_argmax<kBT>(k, bad, sh.keys, &sh.flag);
+    int st = kStatusOk;
+    if (bad)
+        st = kStatusNonfinite;
+    else if (k.slot < 0 || k.value == 0.0)
+        st = kStatusSingular;
+    if (tid == 0) {
+        r.piv_pos[s] = k.slot;
+        r.piv_val[s] = k.value;
+        if (st == kStatusOk) {
+            const int a = r.perm[s];
+            r.perm[s] = r.perm[k.slot];
+            r.perm[k.slot] = a;
+        }
+    }
+    if (st == kStatusOk) {
+        const T p = (T)k.value;
+        const T vs = (T)sh.vs;
+        const int64_t l = k.slot;
+        for (int64_t j = s + tid; j < n; j += kBT) {
+            const T v = row[j];
+            row[j] = (j == s) ? p : ((j == l) ? vs : v) / p;
+        }
+    }
+    __syncthreads();
+    return st;
+}
+
+// Step s inside the panel [s0, pend): exchange positions s, l in the
+// earlier panel rows; update the later panel rows (one wavefront per row).
+template <typename T>
+__device__ void wg_panel_update(Region<T>& r, int64_t n, int64_t s,
+                                int64_t s0, int64_t pend, int64_t l)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    T* W = r.W;
+    const int64_t ldw = r.ldw;
+    if (l != s)
+        for (int64_t u = s0 + tid; u < s; u += kBT) {
+            T* ru = W + u * ldw;
+            const T a = ru[s];
+            ru[s] = ru[l];
+            ru[l] = a;
+        }
+    const T* rs = W + s * ldw;
+    for (int64_t i = s + 1 + wid; i < pend; i += kBT / kWave) {
+        T* ri = W + i * ldw;
+        const T c = ri[l]; // every lane reads it before any lane writes
+        for (int64_t j = s + 1 + lane; j < n; j += kWave) {
+            T x;
+            if (j == l) {
+                x = ri[s];
+                ri[s] = c;
+            } else {
+                x = ri[j];
+            }
+            ri[j] = fma(-c, rs[j], x);
+        }
+    }
+    __syncthreads();
+}
+
+// Sources of the moved columns for the rows below the panel, and the
+// inverses of U11's 16 x 16 diagonal blocks (as blk_perm).
+template <typename T>
+__device__ void wg_perm(Region<T>& r, int64_t n, int64_t s0, int nb)
+{
+    const int tid = threadIdx.x;
+    const int64_t pend = s0 + nb;
+    for (int64_t j = pend + tid; j < n; j += kBT) r.colsrc[j] = (int)j;
+    __syncthreads();
+    auto trace = [&](int64_t d) -> int {
+        int64_t pos = d;
+        for (int u = nb - 1; u >= 0; --u) {
+            const int64_t a = s0 + u, b = r.piv_pos[s0 + u];
+            if (pos == a)
+                pos = b;
+            else if (pos == b)
+                pos = a;
+        }
+        return (int)pos;
+    };
+    for (int t = tid; t < nb; t += kBT) {
+        r.srcp[t] = trace(s0 + t);
+        const int64_t d = r.piv_pos[s0 + t];
+        if (d >= pend) r.colsrc[d] = trace(d);
+    }
+    const int nblk = (nb + 15) / 16;
+    const T* U = r.W + s0 * r.ldw + s0;
+    for (int e = tid; e < nblk * 16; e += kBT) {
+        const int J = e >> 4, c = e & 15;
+        T x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = (q == c) ? T(1) : T(0);
+#pragma unroll
+        for (int q = 14; q >= 0; --q) {
+            if (q >= c) continue;
+            T sum = 0;
+#pragma unroll
+            for (int v = q + 1; v < 16; ++v) {
+                if (v > c) break;
+                const int pv = 16 * J + v;
+                const T u = (pv < nb) ? U[(int64_t)(16 * J + q) * r.ldw + pv] : T(0);
+                sum = fma(u, x[v], sum);
+            }
+            x[q] = -sum;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) r.dinv[(J * 16 + q) * 16 + c] = x[q];
+    }
+    __syncthreads();
+}
+
+// L21 = gather(A21) * U11^{-1}, 64 rows per pass (16 per wavefront), as
+// blk_trsm_mfma.  X: LDS, 4 x 16 x (nblk*16 + 1) elements.
+template <typename T>
+__device__ void wg_trsm(Region<T>& r, int64_t n, int64_t s0, int nb, T* Xall)
+{
+    using P = typename MfmaFor<T>::P;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nblk = (nb + 15) / 16;
+    const int xld = nblk * 16 + 1;
+    T* X = Xall + wid * 16 * xld;
+    const int64_t pend = s0 + nb;
+    const T* W = r.W;
+    const int64_t ldw = r.ldw;
+    const T* U = W + s0 * ldw + s0;
+    const int cin = lane & 15, kl = lane >> 4;
+    for (int64_t g0 = pend; g0 < n; g0 += 64) {
+        const int64_t i0 = g0 + wid * 16;
+        for (int J = 0; J < nblk; ++J) {
+            const int t = 16 * J + cin;
+            typename P::Acc acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = i0 + P::drow(lane, q);
+                acc[q] = (row < n && t < nb) ? W[row * ldw + r.srcp[t]] : T(0);
+            }
+            for (int K = 0; K < J; ++K) {
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq) {
+                    const int k = 16 * K + 4 * kq + kl;
+                    const T a = -X[cin * xld + k];
+                    const T b = (t < nb) ? U[(int64_t)k * ldw + t] : T(0);
+                    acc = P::mma(a, b, acc);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[P::drow(lane, q) * xld + 16 * J + cin] = acc[q];
+            __syncthreads();
+            typename P::Acc x = {0, 0, 0, 0};
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) {
+                const T a = X[cin * xld + 16 * J + 4 * kq + kl];
+                const T b = r.dinv[(J * 16 + 4 * kq + kl) * 16 + cin];
+                x = P::mma(a, b, x);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[P::drow(lane, q) * xld + 16 * J + cin] = x[q];
+            __syncthreads();
+        }
+        for (int e = lane; e < 16 * nb; e += kWave) {
+            const int ii = e / nb, tt = e - ii * nb;
+            const int64_t row = i0 + ii;
+            if (row < n) r.L[(row - pend) * nb + tt] = X[ii * xld + tt];
+        }
+        __syncthreads();
+    }
+}
+
+// Trailing update C[pend:, pend:] <- C[., colsrc] - L U12 with tiles of
+// (32 WT) x (32 WT): 4 wavefronts in 2 x 2, WT x WT MFMA tiles each.
+template <typename T, int WT>
+__device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
+                               T* lds)
+{
+    using P = typename MfmaFor<T>::P;
+    constexpr int BT = 32 * WT;
+    constexpr int KC = 16;
+    constexpr int LD = BT + 16;
+    T* As = lds;            // [KC][LD]
+    T* Bs = lds + KC * LD;  // [KC][LD]
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1;
+    const int cin = lane & 15, kl = lane >> 4;
+    const int64_t pend = s0 + nb, M = n - pend;
+    const int64_t tiles = (M + BT - 1) / BT;
+    const T* U = r.W + s0 * r.ldw;
+    for (int64_t t = 0; t < tiles * tiles; ++t) {
+        const int64_t rb = (t / tiles) * BT, cb = (t % tiles) * BT;
+        typename P::Acc acc[WT][WT];
+#pragma unroll
+        for (int a = 0; a < WT; ++a)
+#pragma unroll
+            for (int b = 0; b < WT; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[a][b][q] = T(0);
+        for (int k0 = 0; k0 < nb; k0 += KC) {
+            for (int e = tid; e < BT * KC; e += kBT) {
+                const int rr = e / KC, kk = e - rr * KC;
+                const int64_t row = rb + rr;
+                As[kk * LD + rr] = (row < M && k0 + kk < nb)
+                                       ? -r.L[row * nb + k0 + kk]
+                                       : T(0);
+                const int kb = e / BT, cc = e - kb * BT;
+                const int64_t col = cb + cc;
+                Bs[kb * LD + cc] = (col < M && k0 + kb < nb)
+                                       ? U[(int64_t)(k0 + kb) * r.ldw + pend + col]
+                                       : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kq = 0; kq < KC; kq += 4) {
+                T a[WT], b[WT];
+#pragma unroll
+                for (int q = 0; q < WT; ++q) {
+                    a[q] = As[(kq + kl) * LD + wm * 16 * WT + q * 16 + cin];
+                    b[q] = Bs[(kq + kl) * LD + wn * 16 * WT + q * 16 + cin];
+                }
+#pragma unroll
+                for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < WT; ++tj)
+                        acc[ti][tj] = P::mma(a[ti], b[tj], acc[ti][tj]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj) {
+            const int64_t col = cb + wn * 16 * WT + tj * 16 + cin;
+            if (col >= M) continue;
+            const int64_t src = r.colsrc[pend + col];
+#pragma unroll
+            for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t row = rb + wm * 16 * WT + ti * 16 + P::drow(lane, q);
+                    if (row < M) {
+                        T* crow = r.W + (pend + row) * r.ldw;
+                        crow[pend + col] = crow[src] + acc[ti][tj][q];
+                    }
+                }
+        }
+    }
+    __syncthreads();
+}
+
+// Split-BF16 x 3 form of the trailing update (FP32 storage).
+template <int WT>
+__device__ void wg_gemm_bf16x3(Region<float>& r, int64_t n, int64_t s0, int nb,
+                               float* lds_f)
+{
+    constexpr int BT = 32 * WT;
+    constexpr int KC = 32;
+    constexpr int LD = KC + 8;
+    __bf16* Ah = reinterpret_cast<__bf16*>(lds_f);
+    __bf16* Al = Ah + BT * LD;
+    __bf16* Bh = Al + BT * LD;
+    __bf16* Bl = Bh + BT * LD;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1;
+    const int cin = lane & 15, kg = lane >> 4;
+    const int64_t pend = s0 + nb, M = n - pend;
+    const int64_t tiles = (M + BT - 1) / BT;
+    const float* U = r.W + s0 * r.ldw;
+    for (int64_t t = 0; t < tiles * tiles; ++t) {
+        const int64_t rb = (t / tiles) * BT, cb = (t % tiles) * BT;
+        f4 acc[WT][WT];
+#pragma unroll
+        for (int a = 0; a < WT; ++a)
+#pragma unroll
+            for (int b = 0; b < WT; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < nb; k0 += KC) {
+            for (int e = tid; e < BT * KC; e += kBT) {
+                const int rr = e / KC, kk = e - rr * KC;
+                const int64_t row = rb + rr;
+                const float va = (row < M && k0 + kk < nb)
+                                     ? -r.L[row * nb + k0 + kk]
+                                     : 0.0f;
+                const __bf16 ha = (__bf16)va;
+                Ah[rr * LD + kk] = ha;
+                Al[rr * LD + kk] = (__bf16)(va - (float)ha);
+                const int kb = e / BT, cc = e - kb * BT;
+                const int64_t col = cb + cc;
+                const float vb = (col < M && k0 + kb < nb)
+                                     ? U[(int64_t)(k0 + kb) * r.ldw + pend + col]
+                                     : 0.0f;
+                const __bf16 hb = (__bf16)vb;
+                Bh[cc * LD + kb] = hb;
+                Bl[cc * LD + kb] = (__bf16)(vb - (float)hb);
+            }
+            __syncthreads();
+            bf8 ah[WT], al[WT], bh[WT], bl[WT];
+#pragma unroll
+            for (int q = 0; q < WT; ++q) {
+                const int ar = wm * 16 * WT + q * 16 + cin;
+                const int bc = wn * 16 * WT + q * 16 + cin;
+                ah[q] = *reinterpret_cast<const bf8*>(&Ah[ar * LD + 8 * kg]);
+                al[q] = *reinterpret_cast<const bf8*>(&Al[ar * LD + 8 * kg]);
+                bh[q] = *reinterpret_cast<const bf8*>(&Bh[bc * LD + 8 * kg]);
+                bl[q] = *reinterpret_cast<const bf8*>(&Bl[bc * LD + 8 * kg]);
+            }
+#pragma unroll
+            for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < WT; ++tj) {
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        al[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        ah[ti], bl[tj], acc[ti][tj], 0, 0, 0);
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        ah[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+                }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj) {
+            const int64_t col = cb + wn * 16 * WT + tj * 16 + cin;
+            if (col >= M) continue;
+            const int64_t src = r.colsrc[pend + col];
+#pragma unroll
+            for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t row = rb + wm * 16 * WT + ti * 16 + 4 * kg + q;
+                    if (row < M) {
+                        float* crow = r.W + (pend + row) * r.ldw;
+                        crow[pend + col] = crow[src] + acc[ti][tj][q];
+                    }
+                }
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void wg_trailing(Region<T>& r, int64_t n, int64_t s0, int nb,
+                            int tile, int update, T* lds);
+
+template <>
+__device__ void wg_trailing<double>(Region<double>& r, int64_t n, int64_t s0,
+                                    int nb, int tile, int update, double* lds)
+{
+    (void)update;
+    if (tile >= 64)
+        wg_gemm_scalar<double, 2>(r, n, s0, nb, lds);
+    else
+        wg_gemm_scalar<double, 1>(r, n, s0, nb, lds);
+}
+
+template <>
+__device__ void wg_trailing<float>(Region<float>& r, int64_t n, int64_t s0,
+                                   int nb, int tile, int update, float* lds)
+{
+    if (update == MC_UPDATE_BF16X3) {
+        if (tile >= 64)
+            wg_gemm_bf16x3<2>(r, n, s0, nb, lds);
+        else
+            wg_gemm_bf16x3<1>(r, n, s0, nb, lds);
+    } else {
+        if (tile >= 64)
+            wg_gemm_scalar<float, 2>(r, n, s0, nb, lds);
+        else
+            wg_gemm_scalar<float, 1>(r, n, s0, nb, lds);
+    }
+}
+
+// Whole condensation of one matrix by one workgroup.
+template <typename T>
+__device__ void wg_factor(const T* __restrict__ A, int64_t n, int64_t lda,
+                          int64_t b, int tile, int update,
+                          unsigned char* region, mc_result* out, WgShared& sh,
+                          T* lds)
+{
+    const int tid = threadIdx.x;
+    if (n == 0) {
+        if (tid == 0) {
+            out->logabsdet = 0.0;
+            out->sign = 1.0;
+            out->info = 0;
+        }
+        return;
+    }
+    Region<T> r = carve_region<T>(region, n, b);
+    for (int64_t i = tid >> 6; i < n; i += kBT / kWave)
+        for (int64_t j = tid & 63; j < n; j += kWave)
+            r.W[i * r.ldw + j] = A[i * lda + j];
+    for (int64_t j = tid; j < n; j += kBT) r.perm[j] = (int)j;
+    __syncthreads();
+
+    int st = kStatusOk;
+    int64_t bad_step = 0;
+    for (int64_t s0 = 0; s0 < n && st == kStatusOk; s0 += b) {
+        const int nb = (int)((b < n - s0) ? b : (n - s0));
+        const int64_t pend = s0 + nb;
+        st = wg_pivot_row<T>(r, n, s0, sh);
+        if (st != kStatusOk) {
+            bad_step = s0;
+            break;
+        }
+        for (int64_t s = s0; s < pend; ++s) {
+            const int64_t l = r.piv_pos[s];
+            wg_panel_update<T>(r, n, s, s0, pend, l);
+            if (s + 1 < pend) {
+                st = wg_pivot_row<T>(r, n, s + 1, sh);
+                if (st != kStatusOk) {
+                    bad_step = s + 1;
+                    break;
+                }
+            }
+        }
+        if (st != kStatusOk || pend >= n) break;
+        wg_perm<T>(r, n, s0, nb);
+        wg_trsm<T>(r, n, s0, nb, lds);
+        wg_trailing<T>(r, n, s0, nb, tile, update, lds);
+    }
+
+    // compensated sum of log|p| and sign parity (as blk_finalize)
+    if (st != kStatusOk) {
+        if (tid == 0) {
+            const bool sing = st == kStatusSingular;
+            out->logabsdet = sing ? -INFINITY : NAN;
+            out->sign = 0.0;
+            out->info = sing ? bad_step + 1 : (int64_t)MC_INFO_NONFINITE;
+        }
+        __syncthreads();
+        return;
+    }
+    Compensated acc{0.0, 0.0};
+    int par = 0;
+    for (int64_t s = tid; s < n; s += kBT) {
+        const double p = r.piv_val[s];
+        comp_add(acc, log(fabs(p)));
+        par ^= (p < 0.0) ? 1 : 0;
+        par ^= (r.piv_pos[s] != (int)s) ? 1 : 0;
+    }
+    sh.csum[tid] = acc.sum;
+    sh.ccomp[tid] = acc.comp;
+    sh.cpar[tid] = par;
+    __syncthreads();
+    if (tid == 0) {
+        Compensated tot{0.0, 0.0};
+        int pp = 0;
+        for (int t = 0; t < kBT; ++t) {
+            comp_merge(tot, Compensated{sh.csum[t], sh.ccomp[t]});
+            pp ^= sh.cpar[t];
+        }
+        const double la = tot.sum + tot.comp;
+        if (!isfinite(la)) {
+            out->logabsdet = NAN;
+            out->sign = 0.0;
+            out->info = MC_INFO_NONFINITE;
+        } else {
+            out->logabsdet = la;
+            out->sign = pp ? -1.0 : 1.0;
+            out->info = 0;
+        }
+    }
+    __syncthreads();
+}
+
+// The persistent kernel: grid = resident workgroups; each loops over the
+// queue until it is empty.  Every workgroup reaches the exit.
+template <typename T>
+__global__ void __launch_bounds__(kBT)
+batched_persistent(BatchArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ WgShared sh;
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    for (;;) {
+        if (threadIdx.x == 0) sh.qidx = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int q = sh.qidx;
+        __syncthreads();
+        if (q >= a.batch) break;
+        const int k = a.order[q];
+        const int64_t n = a.n_array[k];
+        if (n < 0 || n > a.n_max || a.lda_array[k] < (n > 1 ? n : 1) ||
+            (n > 0 && a.A_array[k] == nullptr)) {
+            if (threadIdx.x == 0) {
+                a.out[k].logabsdet = NAN;
+                a.out[k].sign = 0.0;
+                a.out[k].info = MC_INFO_BADARG;
+            }
+            continue;
+        }
+        const int bk = bucket_of(n);
+        const int64_t b = a.table.b[bk];
+        const int tile = a.table.tile[bk];
+        unsigned char* region = a.regions + (size_t)k * a.region_stride;
+        wg_factor<T>(static_cast<const T*>(a.A_array[k]), n, a.lda_array[k],
+                     b, tile, a.update, region, a.out + k, sh, lds);
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t)
+{
+    const int elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    size_t best = 0;
+    for (int k = 0; k < kTuneBuckets; ++k)
+        best = std::max(best, bat_region_bytes(n_max, t.b[k], elem));
+    return best;
+}
+
+size_t batched_lds_bytes(int dtype, const TuneTable& t)
+{
+    const int elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    int64_t bmax = 16;
+    for (int k = 0; k < kTuneBuckets; ++k) bmax = std::max<int64_t>(bmax, t.b[k]);
+    const size_t trsm = (size_t)elem * 64 * (size_t)(((bmax + 15) / 16) * 16 + 1);
+    const size_t gemm = (size_t)elem * 2 * 16 * (64 + 16);
+    const size_t bf16 = 4 * 64 * (32 + 8) * 2;
+    return std::max(trsm, std::max(gemm, bf16));
+}
+
+hipError_t launch_batched(const BatchArgs& a, int dtype, size_t lds_bytes,
+                          hipStream_t stream)
+{
+    hipLaunchKernelGGL(batched_setup, dim3(1), dim3(kBT), 0, stream,
+                       a.n_array, a.batch, a.counter, a.order);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return note_hip_error(e);
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return note_hip_error(e);
+    const int64_t grid = std::min<int64_t>((int64_t)cus * 2, std::max<int64_t>(a.batch, 1));
+    // dynamic LDS above the 64 KB default needs the attribute raised to the
+    // exact size (static LDS of the kernel adds to it within 160 KB)
+    if (dtype == MC_DTYPE_F64) {
+        if (lds_bytes > 64 * 1024) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batched_persistent<double>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            if (e != hipSuccess) return note_hip_error(e);
+        }
+        hipLaunchKernelGGL(batched_persistent<double>, dim3((unsigned)grid), dim3(kBT),
+                           lds_bytes, stream, a);
+    } else {
+        if (lds_bytes > 64 * 1024) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batched_persistent<float>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            if (e != hipSuccess) return note_hip_error(e);
+        }
+        hipLaunchKernelGGL(batched_persistent<float>, dim3((unsigned)grid), dim3(kBT),
+                           lds_bytes, stream, a);
+    }
+    return note_hip_error(hipGetLastError());
+}
+
+} // namespace mc

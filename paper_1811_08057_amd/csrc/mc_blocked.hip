@@ -25,26 +25,28 @@
 //   blk_step   one step on the panel rows; the block owning the next panel
 //              row also finds and factors the next pivot (lookahead)
 //   blk_perm   source position of every column the exchanges moved
-//   blk_trsm   L21 = gather(A21) * U11^{-1}
+//   blk_trsm_mfma  L21 = gather(A21) * U11^{-1} on the matrix cores
 //   gemm       A22 <- gather(A22) - L21 * U12    (mc_gemm.hip)
 #include <algorithm>
 
 #include "mc_device.h"
 #include "mc_gemm.h"
 #include "mc_internal.h"
+#include "mc_mfma.h"
 
 namespace mc {
 
 constexpr int kBlkThreads = 256;
-constexpr int kTrsmRows = 64; // rows per solve block (4 lanes per row)
+constexpr int kTrsmRows = 64; // rows per solve block (16 per wavefront)
 
 template <typename T>
 __global__ void __launch_bounds__(kBlkThreads)
 blk_init(const T* __restrict__ A, int64_t lda, int64_t n, BlkWork<T> w)
 {
     const int64_t i = blockIdx.x;
-    for (int64_t j = threadIdx.x; j < n; j += kBlkThreads)
-        w.W[i * w.ldw + j] = A[i * lda + j];
+    if (A != w.W) // in-place factorisation: the caller's matrix is W
+        for (int64_t j = threadIdx.x; j < n; j += kBlkThreads)
+            w.W[i * w.ldw + j] = A[i * lda + j];
     if (i == 0) {
         for (int64_t j = threadIdx.x; j < n; j += kBlkThreads) {
             w.perm[j] = (int)j;
@@ -177,24 +179,229 @@ blk_step(int64_t n, int64_t s, int64_t s0, int64_t pend, BlkWork<T> w)
     record_and_factor(w, n, s + 1, k, bad, shv, &shstatus);
 }
 
+// ---- register-resident step kernels (rows up to kStepThreads * 16 wide) ----
+//
+// One block of kStepThreads threads per row; thread t holds the entries at
+// positions j0 + t + e * kStepThreads, e < EPT, in registers.  Every load is
+// issued before the block's single barrier, so a step costs about one memory
+// latency plus the argmax reduction.
+
+constexpr int kStepThreads = 1024;
+
+// Decide the step's status from the reduced key (same on every thread).
+__device__ __forceinline__ int pivot_status(const PivotKey& k, bool bad)
+{
+    if (bad) return kStatusNonfinite;
+    if (k.slot < 0 || k.value == 0.0) return kStatusSingular;
+    return kStatusOk;
+}
+
+// Thread 0's bookkeeping for the pivot of step s (runs beside the
+// factoring stores of the other threads).
+template <typename T>
+__device__ __forceinline__ void record_pivot(BlkWork<T>& w, int64_t s,
+                                             const PivotKey& k, int st)
+{
+    w.piv_pos[s] = k.slot;
+    w.piv_val[s] = k.value;
+    if (st == kStatusOk) {
+        const int a = w.perm[s];
+        w.perm[s] = w.perm[k.slot];
+        w.perm[k.slot] = a;
+    } else {
+        w.state->bad_step = (int)s;
+        w.state->status = st;
+    }
+}
+
+// Write row s (values y[] at positions s + tid + e*NT) in factored form.
+template <typename T, int EPT>
+__device__ __forceinline__ void store_factored(T* row, int64_t s, int64_t n,
+                                               const T (&y)[EPT], T p,
+                                               int64_t l, T vs)
+{
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s + threadIdx.x + (int64_t)e * kStepThreads;
+        if (j < n) row[j] = (j == s) ? p : ((j == l) ? vs : y[e]) / p;
+    }
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kStepThreads)
+blk_head_r(int64_t n, int64_t s, BlkWork<T> w)
+{
+    __shared__ PivotKey sh[kStepThreads / kWave];
+    __shared__ int shflag;
+    __shared__ T shv;
+    if (w.state->status != kStatusOk) return;
+    T* row = w.W + s * w.ldw;
+    T y[EPT];
+    int pc[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s + threadIdx.x + (int64_t)e * kStepThreads;
+        if (j < n) {
+            y[e] = row[j];
+            pc[e] = w.perm[j];
+        }
+    }
+    if (threadIdx.x == 0) shv = y[0];
+    PivotKey k = no_candidate();
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s + threadIdx.x + (int64_t)e * kStepThreads;
+        if (j < n && !offer(k, (double)y[e], pc[e], (int)j)) bad = true;
+    }
+    k = block_argmax<kStepThreads>(k, bad, sh, &shflag);
+    const int st = pivot_status(k, bad);
+    if (threadIdx.x == 0) record_pivot(w, s, k, st);
+    if (st != kStatusOk) return;
+    store_factored<T, EPT>(row, s, n, y, (T)k.value, k.slot, shv);
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kStepThreads)
+blk_step_r(int64_t n, int64_t s, int64_t s0, int64_t pend, BlkWork<T> w)
+{
+    __shared__ PivotKey sh[kStepThreads / kWave];
+    __shared__ int shflag;
+    __shared__ T shv;
+    if (w.state->status != kStatusOk) return;
+    const int tid = threadIdx.x;
+    const int64_t l = w.piv_pos[s];
+    T* __restrict__ W = w.W;
+    const int64_t ldw = w.ldw;
+    if (blockIdx.x == 0 && l != s) {
+        for (int64_t u = s0 + tid; u < s; u += kStepThreads) {
+            T* ru = W + u * ldw;
+            const T a = ru[s];
+            const T b = ru[l];
+            ru[s] = b;
+            ru[l] = a;
+        }
+    }
+    const int64_t i = s + 1 + blockIdx.x;
+    if (i >= pend) return;
+    const T* rs = W + s * ldw;
+    T* ri = W + i * ldw;
+    const bool look = (blockIdx.x == 0);
+    // every load first: the multiplier, the row, the pivot row, column ids
+    const T c = ri[l];
+    T x[EPT], r[EPT];
+    int pc[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s + 1 + tid + (int64_t)e * kStepThreads;
+        if (j < n) {
+            x[e] = ri[(j == l) ? s : j];
+            r[e] = rs[j];
+            if (look) pc[e] = w.perm[j];
+        }
+    }
+    __syncthreads(); // no position of row i is written before all reads
+    T y[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) y[e] = fma(-c, r[e], x[e]);
+    if (tid == 0 && l != s) ri[s] = c; // the multiplier moves to position s
+    if (!look) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t j = s + 1 + tid + (int64_t)e * kStepThreads;
+            if (j < n) ri[j] = y[e];
+        }
+        return;
+    }
+    if (tid == 0) shv = y[0];
+    PivotKey k = no_candidate();
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s + 1 + tid + (int64_t)e * kStepThreads;
+        if (j < n && !offer(k, (double)y[e], pc[e], (int)j)) bad = true;
+    }
+    k = block_argmax<kStepThreads>(k, bad, sh, &shflag);
+    const int st = pivot_status(k, bad);
+    if (tid == 0) record_pivot(w, s + 1, k, st);
+    if (st != kStatusOk) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t j = s + 1 + tid + (int64_t)e * kStepThreads;
+            if (j < n) ri[j] = y[e];
+        }
+        return;
+    }
+    store_factored<T, EPT>(ri, s + 1, n, y, (T)k.value, k.slot, shv);
+}
+
+// Elements per thread for a row of `width` active entries, or 0 when the
+// row is wider than the register-resident kernels handle.
+static int step_ept(int64_t width)
+{
+    for (int e = 1; e <= 16; e *= 2)
+        if (width <= (int64_t)e * kStepThreads) return e;
+    return 0;
+}
+
+template <typename T>
+static void launch_head(int64_t n, int64_t s, const BlkWork<T>& w,
+                        hipStream_t stream)
+{
+    switch (step_ept(n - s)) {
+#define MC_HEAD(E)                                                            \
+    case E:                                                                   \
+        hipLaunchKernelGGL((blk_head_r<T, E>), dim3(1), dim3(kStepThreads),  \
+                           0, stream, n, s, w);                               \
+        return;
+        MC_HEAD(1) MC_HEAD(2) MC_HEAD(4) MC_HEAD(8) MC_HEAD(16)
+#undef MC_HEAD
+    default:
+        hipLaunchKernelGGL(blk_head<T>, dim3(1), dim3(kBlkThreads), 0, stream,
+                           n, s, w);
+    }
+}
+
+template <typename T>
+static void launch_step(int64_t n, int64_t s, int64_t s0, int64_t pend,
+                        const BlkWork<T>& w, hipStream_t stream)
+{
+    const int64_t blocks = std::max<int64_t>(1, pend - 1 - s);
+    switch (step_ept(n - s - 1)) {
+#define MC_STEP(E)                                                            \
+    case E:                                                                   \
+        hipLaunchKernelGGL((blk_step_r<T, E>), dim3((unsigned)blocks),       \
+                           dim3(kStepThreads), 0, stream, n, s, s0, pend, w); \
+        return;
+        MC_STEP(1) MC_STEP(2) MC_STEP(4) MC_STEP(8) MC_STEP(16)
+#undef MC_STEP
+    default:
+        hipLaunchKernelGGL(blk_step<T>, dim3((unsigned)blocks),
+                           dim3(kBlkThreads), 0, stream, n, s, s0, pend, w);
+    }
+}
+
 // For the rows below the panel, where did each moved column come from?
 // Position s0+t exchanged contents with position l_t at step s0+t, so the
 // source of a destination is found by undoing the exchanges in reverse.
+// The same block also inverts the 16 x 16 diagonal blocks of the unit upper
+// triangle U11 of the factored panel (back substitution, one column per
+// thread), for the triangular solve below.
+template <typename T>
 __global__ void __launch_bounds__(kBlkThreads)
-blk_perm(int64_t s0, int nb, const int* __restrict__ piv_pos, int* colsrc,
-         int* srcp, int* moved, const DevState* state)
+blk_perm(int64_t s0, int nb, BlkWork<T> w)
 {
     __shared__ int lp[kMaxPanel];
-    if (state->status != kStatusOk) return;
+    if (w.state->status != kStatusOk) return;
     const int tid = threadIdx.x;
     for (int t = tid; t < kMaxPanel; t += kBlkThreads) {
-        const int d = moved[t];
+        const int d = w.moved[t];
         if (d >= 0) {
-            colsrc[d] = d;
-            moved[t] = -1;
+            w.colsrc[d] = d;
+            w.moved[t] = -1;
         }
     }
-    for (int t = tid; t < nb; t += kBlkThreads) lp[t] = piv_pos[s0 + t];
+    for (int t = tid; t < nb; t += kBlkThreads) lp[t] = w.piv_pos[s0 + t];
     __syncthreads();
     const int64_t pend = s0 + nb;
     auto trace = [&](int64_t d) -> int {
@@ -209,57 +416,152 @@ blk_perm(int64_t s0, int nb, const int* __restrict__ piv_pos, int* colsrc,
         return (int)pos;
     };
     for (int t = tid; t < nb; t += kBlkThreads) {
-        srcp[t] = trace(s0 + t);
+        w.srcp[t] = trace(s0 + t);
         const int64_t d = lp[t];
         if (d >= pend) {
-            colsrc[d] = trace(d);
-            moved[t] = (int)d;
+            w.colsrc[d] = trace(d);
+            w.moved[t] = (int)d;
         }
+    }
+    // diagonal-block inverses: column c of block J solves U_JJ x = e_c
+    const int nblk = (nb + 15) / 16;
+    const T* U = w.W + s0 * w.ldw + s0;
+    for (int e = tid; e < nblk * 16; e += kBlkThreads) {
+        const int J = e >> 4, c = e & 15;
+        T x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = (r == c) ? T(1) : T(0);
+#pragma unroll
+        for (int r = 14; r >= 0; --r) {
+            if (r >= c) continue;
+            T sum = 0;
+#pragma unroll
+            for (int v = r + 1; v < 16; ++v) {
+                if (v > c) break;
+                const int pr = 16 * J + r, pv = 16 * J + v;
+                const T u = (pv < nb) ? U[(int64_t)pr * w.ldw + pv] : T(0);
+                sum = fma(u, x[v], sum);
+            }
+            x[r] = -sum;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) w.dinv[(J * 16 + r) * 16 + c] = x[r];
     }
 }
 
-// L21 = A21 * U11^{-1}: for each row below the panel, x solves x U11 = a
-// with a_t = W[i][srcp[t]] and U11 the unit upper triangle of the factored
-// panel rows:  x_t = a_t - sum_{u<t} x_u U11[u][t].  Four lanes share a
-// row (lane q handles u = q mod 4); U11 is packed by columns in LDS.
+// L21 = A21 * U11^{-1} on the matrix cores, one wavefront per 16 rows, in
+// 16-column blocks J (forward substitution by blocks):
+//     R_J = A21[:, J] - sum_{K<J} X_K U11[K, J]      (MFMA, K = 16 per block)
+//     X_J = R_J * inv(U11[J, J])                     (MFMA)
+// with A21[i][t] = W[i][srcp[t]] (the exchanges folded into the load).  X is
+// kept per wavefront in LDS; rows past n and columns past nb are zeros.
 template <typename T>
 __global__ void __launch_bounds__(kBlkThreads)
-blk_trsm(int64_t n, int64_t s0, int nb, BlkWork<T> w)
+blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
 {
+    using P = typename MfmaFor<T>::P;
     extern __shared__ unsigned char smem_raw[];
-    T* us = reinterpret_cast<T*>(smem_raw);
-    const int packed = nb * (nb - 1) / 2;
-    T* xs = us + packed;
-    const int ldx = nb + 1;
+    const int nblk = (nb + 15) / 16;
+    const int xld = nblk * 16 + 1;
     if (w.state->status != kStatusOk) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    T* X = reinterpret_cast<T*>(smem_raw) + wid * 16 * xld;
+    const int64_t pend = s0 + nb;
+    const int64_t i0 = pend + (int64_t)blockIdx.x * kTrsmRows + wid * 16;
     const T* __restrict__ W = w.W;
     const int64_t ldw = w.ldw;
-    for (int e = tid; e < nb * nb; e += kBlkThreads) {
-        const int u = e / nb, t = e - u * nb;
-        if (u < t) us[t * (t - 1) / 2 + u] = W[(s0 + u) * ldw + s0 + t];
+    const T* U = W + s0 * ldw + s0;
+    const int cin = lane & 15, kl = lane >> 4;
+    for (int J = 0; J < nblk; ++J) {
+        const int t = 16 * J + cin;
+        typename P::Acc acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = i0 + P::drow(lane, r);
+            acc[r] = (row < n && t < nb) ? W[row * ldw + w.srcp[t]] : T(0);
+        }
+        for (int K = 0; K < J; ++K) {
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) {
+                const int k = 16 * K + 4 * kq + kl; // k < 16 J <= t
+                const T a = -X[cin * xld + k];
+                const T b = (t < nb) ? U[(int64_t)k * ldw + t] : T(0);
+                acc = P::mma(a, b, acc);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[P::drow(lane, r) * xld + 16 * J + cin] = acc[r];
+        __syncthreads();
+        typename P::Acc x = {0, 0, 0, 0};
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const T a = X[cin * xld + 16 * J + 4 * kq + kl];
+            const T b = w.dinv[(J * 16 + 4 * kq + kl) * 16 + cin];
+            x = P::mma(a, b, x);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[P::drow(lane, r) * xld + 16 * J + cin] = x[r];
+        __syncthreads();
     }
+    for (int e = lane; e < 16 * nb; e += kWave) {
+        const int ii = e / nb, tt = e - ii * nb;
+        const int64_t row = i0 + ii;
+        if (row < n) w.L[(row - pend) * w.ldl + tt] = X[ii * xld + tt];
+    }
+}
+
+// Factor mode (mc_logdet_factor): after a panel's trailing update, put the
+// rows' multipliers into their places (positions s0..pend-1 of the rows
+// below the panel) ...
+template <typename T>
+__global__ void __launch_bounds__(kBlkThreads)
+blk_store_l(int64_t n, int64_t s0, int nb, BlkWork<T> w)
+{
+    if (w.state->status != kStatusOk) return;
     const int64_t pend = s0 + nb;
-    const int r = tid >> 2, q = tid & 3;
-    const int64_t i = pend + (int64_t)blockIdx.x * kTrsmRows + r;
-    const bool valid = i < n;
-    T* x = xs + r * ldx;
-    if (valid)
-        for (int u = q; u < nb; u += 4) x[u] = W[i * ldw + w.srcp[u]];
-    __syncthreads();
-    for (int t = 0; t < nb; ++t) {
-        const T* ut = us + (t * (t - 1)) / 2;
-        T part = 0;
-        if (valid)
-            for (int u = q; u < t; u += 4) part = fma(x[u], ut[u], part);
-        part += __shfl_xor(part, 1, kWave);
-        part += __shfl_xor(part, 2, kWave);
-        if (valid && q == (t & 3)) x[t] -= part;
+    for (int64_t e = blockIdx.x * (int64_t)kBlkThreads + threadIdx.x;
+         e < (n - pend) * nb; e += (int64_t)gridDim.x * kBlkThreads) {
+        const int64_t i = e / nb, t = e - i * nb;
+        w.W[(pend + i) * w.ldw + s0 + t] = w.L[i * w.ldl + t];
     }
-    if (valid) {
-        T* out = w.L + (i - pend) * w.ldl;
-        for (int u = q; u < nb; u += 4) out[u] = x[u];
+}
+
+// ... and apply the panel's column exchanges to the rows above it (their
+// entries right of s0 are factored-row entries in the pre-panel order).
+// One wavefront per row: every moved value is read before any is written.
+template <typename T>
+__global__ void __launch_bounds__(kBlkThreads)
+blk_swaps_above(int64_t s0, int nb, BlkWork<T> w)
+{
+    if (w.state->status != kStatusOk) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * (kBlkThreads / kWave) + (threadIdx.x >> 6);
+    if (u >= s0) return;
+    T* row = w.W + u * w.ldw;
+    // destinations: s0+t (t < nb) from srcp[t]; moved[t] from colsrc[moved[t]]
+    T v[4];
+    int64_t d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = lane + q * kWave; // 0 .. 255
+        d[q] = -1;
+        if (e < nb) {
+            d[q] = s0 + e;
+            v[q] = row[w.srcp[e]];
+        } else if (e >= kMaxPanel && e - kMaxPanel < nb) {
+            const int t = e - kMaxPanel;
+            const int64_t dm = w.moved[t];
+            if (dm >= 0) {
+                d[q] = dm;
+                v[q] = row[w.colsrc[dm]];
+            }
+        }
     }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (d[q] >= 0) row[d[q]] = v[q];
 }
 
 // Compensated sum of log|p_s|; sign = prod sgn(p_s) * (-1)^(exchanges).
@@ -317,23 +619,24 @@ blk_finalize(int64_t n, const int* __restrict__ piv_pos,
 // ---------------------------------------------------------------- host side
 
 template <typename T>
-static size_t trsm_lds_bytes(int nb)
+static size_t trsm_mfma_lds_bytes(int nb)
 {
-    return sizeof(T) * ((size_t)nb * (nb - 1) / 2 + (size_t)kTrsmRows * (nb + 1));
+    const int nblk = (nb + 15) / 16;
+    return sizeof(T) * (size_t)(kTrsmRows) * (size_t)(nblk * 16 + 1);
 }
 
 template <typename T>
 hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                           int update, BlkWork<T> w, mc_result* out,
-                          hipStream_t stream)
+                          hipStream_t stream, bool factor)
 {
     static bool attr_set = false;
-    if (!attr_set) {
+    if (!attr_set && trsm_mfma_lds_bytes<T>((int)kMaxPanel) > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&blk_trsm<T>),
+            reinterpret_cast<const void*>(&blk_trsm_mfma<T>),
             hipFuncAttributeMaxDynamicSharedMemorySize,
-            (int)trsm_lds_bytes<T>((int)kMaxPanel));
-        if (e != hipSuccess) return e;
+            (int)trsm_mfma_lds_bytes<T>((int)kMaxPanel));
+        if (e != hipSuccess) return note_hip_error(e);
         attr_set = true;
     }
     hipLaunchKernelGGL(blk_init<T>, dim3((unsigned)n), dim3(kBlkThreads), 0,
@@ -341,22 +644,17 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     for (int64_t s0 = 0; s0 < n; s0 += b) {
         const int nb = (int)std::min<int64_t>(b, n - s0);
         const int64_t pend = s0 + nb;
-        hipLaunchKernelGGL(blk_head<T>, dim3(1), dim3(kBlkThreads), 0, stream,
-                           n, s0, w);
-        for (int64_t s = s0; s < pend; ++s) {
-            const int64_t blocks = std::max<int64_t>(1, pend - 1 - s);
-            hipLaunchKernelGGL(blk_step<T>, dim3((unsigned)blocks),
-                               dim3(kBlkThreads), 0, stream, n, s, s0, pend,
-                               w);
-        }
+        launch_head<T>(n, s0, w, stream);
+        for (int64_t s = s0; s < pend; ++s)
+            launch_step<T>(n, s, s0, pend, w, stream);
         if (pend >= n) break;
         const int64_t rows = n - pend;
-        hipLaunchKernelGGL(blk_perm, dim3(1), dim3(kBlkThreads), 0, stream, s0,
-                           nb, w.piv_pos, w.colsrc, w.srcp, w.moved, w.state);
-        hipLaunchKernelGGL(blk_trsm<T>,
-                           dim3((unsigned)((rows + kTrsmRows - 1) / kTrsmRows)),
-                           dim3(kBlkThreads), trsm_lds_bytes<T>(nb), stream, n,
+        hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
                            s0, nb, w);
+        hipLaunchKernelGGL(blk_trsm_mfma<T>,
+                           dim3((unsigned)((rows + kTrsmRows - 1) / kTrsmRows)),
+                           dim3(kBlkThreads), trsm_mfma_lds_bytes<T>(nb), stream,
+                           n, s0, nb, w);
         GemmArgs<T> g;
         g.C = w.W;
         g.ldc = w.ldw;
@@ -378,6 +676,26 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         const double bytes = (double)sizeof(T) *
                              (2.0 * rows * rows + 2.0 * rows * nb);
         prof_end(stream, pm, 1, bytes, flops);
+        if (factor) {
+            hipLaunchKernelGGL(blk_store_l<T>, dim3(1024), dim3(kBlkThreads), 0,
+                               stream, n, s0, nb, w);
+            if (s0 > 0)
+                hipLaunchKernelGGL(blk_swaps_above<T>,
+                                   dim3((unsigned)((s0 + 3) / 4)),
+                                   dim3(kBlkThreads), 0, stream, s0, nb, w);
+        }
+    }
+    // the last panel (no rows below): its exchanges still reach the rows
+    // above it in factor mode
+    if (factor && n > 0) {
+        const int64_t s0 = ((n - 1) / b) * b;
+        const int nb = (int)(n - s0);
+        if (s0 > 0) {
+            hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
+                               s0, nb, w);
+            hipLaunchKernelGGL(blk_swaps_above<T>, dim3((unsigned)((s0 + 3) / 4)),
+                               dim3(kBlkThreads), 0, stream, s0, nb, w);
+        }
     }
     hipLaunchKernelGGL(blk_finalize, dim3(1), dim3(kBlkThreads), 0, stream, n,
                        w.piv_pos, w.piv_val, w.state, out);
@@ -386,9 +704,9 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
 
 template hipError_t launch_blocked<double>(const double*, int64_t, int64_t,
                                            int64_t, int, BlkWork<double>,
-                                           mc_result*, hipStream_t);
+                                           mc_result*, hipStream_t, bool);
 template hipError_t launch_blocked<float>(const float*, int64_t, int64_t,
                                           int64_t, int, BlkWork<float>,
-                                          mc_result*, hipStream_t);
+                                          mc_result*, hipStream_t, bool);
 
 } // namespace mc

@@ -1,63 +1,41 @@
 // mc_gemm.hip -- MFMA kernels for the blocked path's trailing update.
 //
 // Block tile BT x BT of C (BT = 32 * WT), four wavefronts in a 2 x 2 grid,
-// each owning WT x WT tiles of 16 x 16.  C is loaded straight into the
-// accumulators (through colsrc), -L and U stream through LDS in K chunks,
-// and the accumulators are stored back in place.  Per block: 2 * BT^2 * K
+// each owning WT x WT tiles of 16 x 16.  -L and U stream through LDS in K
+// chunks into accumulators that start from zero; the epilogue adds the old
+// C (read through colsrc) and stores in place.  Per block: 2 * BT^2 * K
 // flops against BT^2 * 2 * sizeof(T) bytes of C traffic, so the update is
 // matrix-core bound once K = b is large enough (b/8 flop per byte in FP64).
 //
-// Accumulator layouts on gfx950 (measured):
-//   v_mfma_f64_16x16x4f64:   D(i, j) in lane j + 16 (i mod 4), register i / 4
-//   v_mfma_f32_16x16x4f32:   D(i, j) in lane j + 16 (i / 4),   register i mod 4
-//   v_mfma_f32_16x16x32_bf16: as the f32 one.
-// Operands: A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k (K = 4); for
-// the bf16 form each lane holds k = 8 (lane / 16) + e, e = 0..7.
+// Operand and accumulator layouts: mc_mfma.h.
 #include "mc_gemm.h"
 #include "mc_device.h"
+#include "mc_mfma.h"
 
 #include <algorithm>
 
 namespace mc {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
 constexpr int kGemmThreads = 256;
 
-struct MfmaF64 {
-    using T = double;
-    using Acc = d4;
-    __device__ static int drow(int lane, int r) { return (lane >> 4) + 4 * r; }
-    __device__ static Acc mma(double a, double b, Acc c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-};
-
-struct MfmaF32 {
-    using T = float;
-    using Acc = f4;
-    __device__ static int drow(int lane, int r) { return 4 * (lane >> 4) + r; }
-    __device__ static Acc mma(float a, float b, Acc c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-};
-
 // ---------------------------------------------------------------------------
-// FP64 / FP32: one scalar operand per lane, K = 4 per instruction.
+// FP64 / FP32: one scalar operand per lane, K = 4 per instruction.  The
+// K loop is double-buffered: chunk c+1 is read from global memory into
+// registers while chunk c feeds the matrix cores, then parked in the other
+// LDS buffer; one barrier per chunk.
+// (two blocks per CU: the register budget then covers the 64 FP64
+// accumulators of a 4 x 4 wave tile without spilling)
 template <class P, int WT>
-__global__ void __launch_bounds__(kGemmThreads)
+__global__ void __launch_bounds__(kGemmThreads, 2)
 gemm_scalar(GemmArgs<typename P::T> g)
 {
     using T = typename P::T;
     constexpr int BT = 32 * WT;
     constexpr int KC = 16;
-    constexpr int LDS_LD = BT + 16; // conflict-free fragment reads
-    __shared__ T As[KC][LDS_LD];    // -L, transposed (k major)
-    __shared__ T Bs[KC][LDS_LD];    // U
+    constexpr int LDS_LD = BT + 16;               // conflict-free fragment reads
+    constexpr int PE = BT * KC / kGemmThreads;    // elements per thread per chunk
+    __shared__ T As[2][KC][LDS_LD];               // -L, transposed (k major)
+    __shared__ T Bs[2][KC][LDS_LD];               // U
     if (g.state->status != kStatusOk) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -65,46 +43,58 @@ gemm_scalar(GemmArgs<typename P::T> g)
     const int64_t rb = (int64_t)blockIdx.y * BT, cb = (int64_t)blockIdx.x * BT;
     const int col_in = lane & 15, kq_lane = lane >> 4;
 
+    T pa[PE], pb[PE];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PE; ++p) {
+            const int e = tid + p * kGemmThreads;
+            const int rr = e / KC, kk = e - rr * KC;
+            const int64_t row = rb + rr;
+            pa[p] = (row < g.M && k0 + kk < g.K) ? -g.L[row * g.ldl + k0 + kk]
+                                                 : T(0);
+            const int kb = e / BT, cc = e - kb * BT;
+            const int64_t col = cb + cc;
+            pb[p] = (col < g.N && k0 + kb < g.K)
+                        ? g.U[(int64_t)(k0 + kb) * g.ldu + g.c0 + col]
+                        : T(0);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PE; ++p) {
+            const int e = tid + p * kGemmThreads;
+            const int rr = e / KC, kk = e - rr * KC;
+            As[buf][kk][rr] = pa[p];
+            const int kb = e / BT, cc = e - kb * BT;
+            Bs[buf][kb][cc] = pb[p];
+        }
+    };
+
+    gload(0);
+
+    // the product -L U accumulates from zero; C joins it in the epilogue, so
+    // the K loop holds only accumulators, operands and the prefetch
     typename P::Acc acc[WT][WT];
 #pragma unroll
     for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj) {
-            const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
-            const bool cok = col < g.N;
-            const int64_t src = cok ? g.colsrc[g.c0 + col] : 0;
+        for (int tj = 0; tj < WT; ++tj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = rb + wm * 16 * WT + ti * 16 + P::drow(lane, r);
-                acc[ti][tj][r] = (cok && row < g.M)
-                                     ? g.C[(g.r0 + row) * g.ldc + src]
-                                     : T(0);
-            }
-        }
+            for (int r = 0; r < 4; ++r) acc[ti][tj][r] = T(0);
 
-    for (int k0 = 0; k0 < g.K; k0 += KC) {
-        for (int e = tid; e < BT * KC; e += kGemmThreads) {
-            const int rr = e / KC, kk = e - rr * KC;
-            const int64_t row = rb + rr;
-            As[kk][rr] = (row < g.M && k0 + kk < g.K)
-                             ? -g.L[row * g.ldl + k0 + kk]
-                             : T(0);
-        }
-        for (int e = tid; e < BT * KC; e += kGemmThreads) {
-            const int kk = e / BT, cc = e - kk * BT;
-            const int64_t col = cb + cc;
-            Bs[kk][cc] = (col < g.N && k0 + kk < g.K)
-                             ? g.U[(int64_t)(k0 + kk) * g.ldu + g.c0 + col]
-                             : T(0);
-        }
-        __syncthreads();
+    sstore(0);
+    __syncthreads();
+    const int nch = (g.K + KC - 1) / KC;
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) gload((c + 1) * KC);
 #pragma unroll
         for (int kq = 0; kq < KC; kq += 4) {
             T a[WT], b[WT];
 #pragma unroll
             for (int t = 0; t < WT; ++t) {
-                a[t] = As[kq + kq_lane][wm * 16 * WT + t * 16 + col_in];
-                b[t] = Bs[kq + kq_lane][wn * 16 * WT + t * 16 + col_in];
+                a[t] = As[buf][kq + kq_lane][wm * 16 * WT + t * 16 + col_in];
+                b[t] = Bs[buf][kq + kq_lane][wn * 16 * WT + t * 16 + col_in];
             }
 #pragma unroll
             for (int ti = 0; ti < WT; ++ti)
@@ -112,21 +102,29 @@ gemm_scalar(GemmArgs<typename P::T> g)
                 for (int tj = 0; tj < WT; ++tj)
                     acc[ti][tj] = P::mma(a[ti], b[tj], acc[ti][tj]);
         }
+        if (c + 1 < nch) sstore(buf ^ 1);
         __syncthreads();
     }
 
+    // C[dst] = C[src] + acc.  A moved column's source lies in the panel's
+    // column range, which no block writes; otherwise src == dst and the
+    // same thread reads before it writes.
 #pragma unroll
-    for (int ti = 0; ti < WT; ++ti)
+    for (int tj = 0; tj < WT; ++tj) {
+        const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
+        if (col >= g.N) continue;
+        const int64_t src = g.colsrc[g.c0 + col];
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj) {
-            const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
-            if (col >= g.N) continue;
+        for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = rb + wm * 16 * WT + ti * 16 + P::drow(lane, r);
-                if (row < g.M) g.C[(g.r0 + row) * g.ldc + g.c0 + col] = acc[ti][tj][r];
+                if (row < g.M) {
+                    T* crow = g.C + (g.r0 + row) * g.ldc;
+                    crow[g.c0 + col] = crow[src] + acc[ti][tj][r];
+                }
             }
-        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -160,18 +158,7 @@ gemm_bf16x3(GemmArgs<float> g)
 #pragma unroll
     for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj) {
-            const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
-            const bool cok = col < g.N;
-            const int64_t src = cok ? g.colsrc[g.c0 + col] : 0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = rb + wm * 16 * WT + ti * 16 + 4 * kg + r;
-                acc[ti][tj][r] = (cok && row < g.M)
-                                     ? g.C[(g.r0 + row) * g.ldc + src]
-                                     : 0.0f;
-            }
-        }
+        for (int tj = 0; tj < WT; ++tj) acc[ti][tj] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
     for (int k0 = 0; k0 < g.K; k0 += KC) {
         // A = -L: row-major in global and in LDS (k contiguous)
@@ -218,17 +205,21 @@ gemm_bf16x3(GemmArgs<float> g)
     }
 
 #pragma unroll
-    for (int ti = 0; ti < WT; ++ti)
+    for (int tj = 0; tj < WT; ++tj) {
+        const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
+        if (col >= g.N) continue;
+        const int64_t src = g.colsrc[g.c0 + col];
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj) {
-            const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
-            if (col >= g.N) continue;
+        for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = rb + wm * 16 * WT + ti * 16 + 4 * kg + r;
-                if (row < g.M) g.C[(g.r0 + row) * g.ldc + g.c0 + col] = acc[ti][tj][r];
+                if (row < g.M) {
+                    float* crow = g.C + (g.r0 + row) * g.ldc;
+                    crow[g.c0 + col] = crow[src] + acc[ti][tj][r];
+                }
             }
-        }
+    }
 }
 
 // ---------------------------------------------------------------------------

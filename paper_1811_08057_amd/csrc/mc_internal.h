@@ -46,6 +46,7 @@ struct BlkWork {
     int* colsrc;   // source position of each trailing destination position
     int* srcp;     // source position of each panel column s0 + t
     int* moved;    // trailing positions remapped by the previous panel
+    T* dinv;       // inverses of the 16 x 16 diagonal blocks of U11
     DevState* state;
 };
 
@@ -53,11 +54,12 @@ constexpr int64_t kMaxPanel = 128;
 
 size_t blocked_workspace_bytes(int64_t n, int dtype, int64_t b);
 template <typename T>
-BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b);
+BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b,
+                         bool with_w = true);
 template <typename T>
 hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                           int update, BlkWork<T> w, mc_result* out,
-                          hipStream_t stream);
+                          hipStream_t stream, bool factor = false);
 
 size_t plain_workspace_bytes(int64_t n);
 PlainWork plain_carve(void* work, int64_t n);
@@ -74,6 +76,25 @@ struct ProfMark {
 ProfMark prof_begin(hipStream_t stream);
 void prof_end(hipStream_t stream, ProfMark m, int64_t launches,
               double alg_bytes, double alg_flops);
+
+// Workspace of the backward call: Z (n x ldz) holds L^{-1}, then A^{-1}
+// before the permuted transpose; ident is the identity column map the
+// trailing-update kernel reads.
+template <typename T>
+struct BwdWork {
+    T* Z;
+    int64_t ldz;
+    int* ident;
+    DevState* state;
+};
+
+template <typename T>
+hipError_t launch_backward(const T* LU, int64_t ld, const int* perm, int64_t n,
+                           const double* grad_out, T* G, int64_t ldg,
+                           BwdWork<T> w, hipStream_t st);
+
+// Remember a failing HIP status for mc_last_hip_error(); returns it.
+hipError_t note_hip_error(hipError_t e);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
