@@ -73,6 +73,7 @@ typedef int mc_status;
 
 #define MC_INFO_NONFINITE (-1)
 #define MC_INFO_BADARG (-3) /* batched: this matrix's n / lda / pointer invalid */
+#define MC_INFO_ABORTED (-4) /* an internal bounded wait ran out (a bug) */
 
 /* Library version as major*10000 + minor*100 + patch. */
 int mc_version(void);

@@ -144,9 +144,11 @@ static size_t blocked_bytes(int64_t n, int dtype, int64_t b, bool with_w)
     t += align_up(elem * (size_t)n * (size_t)b, kAlign);       // L
     t += align_up(sizeof(int) * (size_t)n, kAlign);            // piv_pos
     t += align_up(sizeof(double) * (size_t)n, kAlign);         // piv_val
-    t += 2 * align_up(sizeof(int) * (size_t)n, kAlign);        // perm, colsrc
+    t += 3 * align_up(sizeof(int) * (size_t)n, kAlign);        // perm, perm0, colsrc
     t += 2 * align_up(sizeof(int) * (size_t)kMaxPanel, kAlign); // srcp, moved
     t += align_up(elem * (size_t)kMaxPanel * 16, kAlign);       // dinv
+    t += align_up(sizeof(int) * (size_t)kMaxPanel, kAlign);     // stepflag
+    t += align_up(2 * sizeof(int), kAlign);                     // claim
     t += align_up(sizeof(DevState), kAlign);
     return t;
 }
@@ -175,10 +177,13 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b, bool with_w)
     w.piv_pos = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
     w.piv_val = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n));
     w.perm = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
+    w.perm0 = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
     w.colsrc = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
     w.srcp = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.moved = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.dinv = reinterpret_cast<T*>(take(sizeof(T) * (size_t)kMaxPanel * 16));
+    w.stepflag = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
+    w.claim = reinterpret_cast<int*>(take(2 * sizeof(int)));
     w.state = reinterpret_cast<DevState*>(take(sizeof(DevState)));
     return w;
 }

@@ -232,8 +232,14 @@ __global__ void __launch_bounds__(kStepThreads)
 blk_head_r(int64_t n, int64_t s, BlkWork<T> w)
 {
     __shared__ PivotKey sh[kStepThreads / kWave];
-    __shared__ int shflag;
+    __shared__ int shflag, shpc;
     __shared__ T shv;
+    // the panel starting here has not published any later step yet
+    for (int t = threadIdx.x; t < kMaxPanel; t += kStepThreads) w.stepflag[t] = 0;
+    if (threadIdx.x == 0) {
+        w.claim[0] = 0;
+        w.claim[1] = -1;
+    }
     if (w.state->status != kStatusOk) return;
     T* row = w.W + s * w.ldw;
     T y[EPT];
@@ -246,7 +252,10 @@ blk_head_r(int64_t n, int64_t s, BlkWork<T> w)
             pc[e] = w.perm[j];
         }
     }
-    if (threadIdx.x == 0) shv = y[0];
+    if (threadIdx.x == 0) {
+        shv = y[0];
+        shpc = pc[0];
+    }
     PivotKey k = no_candidate();
     bool bad = false;
 #pragma unroll
@@ -259,6 +268,12 @@ blk_head_r(int64_t n, int64_t s, BlkWork<T> w)
     if (threadIdx.x == 0) record_pivot(w, s, k, st);
     if (st != kStatusOk) return;
     store_factored<T, EPT>(row, s, n, y, (T)k.value, k.slot, shv);
+    // the column ids after this step's exchange, for the single-XCD panel
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s + threadIdx.x + (int64_t)e * kStepThreads;
+        if (j < n) w.perm0[j] = (j == s) ? k.colid : ((j == k.slot) ? shpc : pc[e]);
+    }
 }
 
 template <typename T, int EPT>
@@ -335,6 +350,461 @@ blk_step_r(int64_t n, int64_t s, int64_t s0, int64_t pend, BlkWork<T> w)
     store_factored<T, EPT>(ri, s + 1, n, y, (T)k.value, k.slot, shv);
 }
 
+// ---- persistent panel: one launch per panel, rows held in registers ----
+//
+// Block r owns panel row i = s0 + 1 + r and keeps positions s0 .. n-1 of it
+// in registers for the whole panel (thread t holds s0 + t + e*kStepThreads).
+// For each step s < i it waits until the pivot row s is published (thread 0
+// spins on stepflag with an agent-scope acquire, bounded), reads r = row s
+// from memory, exchanges the multiplier c (position l) and the entry at
+// position s through LDS, and applies
+//     a_il <- a_is - c r_l,  a_is <- c,  a_ij <- a_ij - c r_j  (j > s, j != l)
+// The block whose row is the next pivot row finds the pivot, writes its row
+// in factored form, records the pivot and publishes it (release).  Rows
+// published earlier still need the exchanges of later steps; blk_perm's
+// fix-up blocks apply them after the panel.
+//
+// Every inter-block wait is bounded by one second of the 100 MHz real-time
+// counter (a panel step takes microseconds): a wait that runs out marks the
+// factorisation aborted and the kernel drains instead of hanging.
+constexpr uint64_t kWaitTicks = 100000000ull;
+
+__device__ __forceinline__ uint64_t now_ticks()
+{
+    return __builtin_amdgcn_s_memrealtime();
+}
+
+// Relaxed device-scope load: coherent across the XCDs' L2 caches without a
+// fence (used for everything another block published during the kernel).
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// s_waitcnt vmcnt(0) (gfx9 encoding; expcnt and lgkmcnt left at their
+// maxima): every vector memory access of this wavefront has completed.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kStepThreads)
+blk_panel(int64_t n, int64_t s0, int64_t pend, BlkWork<T> w)
+{
+    __shared__ PivotKey sh[kStepThreads / kWave];
+    __shared__ int shflag;
+    __shared__ T sh_c, sh_xs, sh_vi; // sh_vi: own row at position i (never
+                                     // shares a slot with the last step)
+    __shared__ int sh_status;
+    const int tid = threadIdx.x;
+    const int64_t i = s0 + 1 + blockIdx.x; // this block's row
+    T* ri = w.W + i * w.ldw;
+    T v[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s0 + tid + (int64_t)e * kStepThreads;
+        if (j < n) v[e] = ri[j];
+    }
+    for (int64_t s = s0; s < i; ++s) {
+        if (s > s0 && tid == 0) {
+            long spins = 0;
+            const uint64_t t0 = now_ticks();
+            // poll with device-coherent loads and no acquire fence (a fence
+            // per poll would invalidate this XCD's L2 under every block)
+            while (__hip_atomic_load(&w.stepflag[s - s0], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                ++spins;
+                if ((spins & 255) == 0 && now_ticks() - t0 > kWaitTicks) {
+                    __hip_atomic_store(&w.state->status, (int)kStatusAborted,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                if ((spins & 1023) == 0 &&
+                    __hip_atomic_load(&w.state->status, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT) != kStatusOk)
+                    break; // another block stopped the factorisation
+                __builtin_amdgcn_s_sleep(1);
+            }
+            sh_status = __hip_atomic_load(&w.state->status, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (s == s0 && tid == 0) sh_status = w.state->status;
+        __syncthreads();
+        if (sh_status != kStatusOk) return; // uniform across the block
+        // the published row and pivot are read with device-coherent loads
+        // (no acquire fence: that would invalidate this XCD's whole L2)
+        const int64_t l = ld_agent(&w.piv_pos[s]);
+        const T* rs = w.W + s * w.ldw;
+        T r[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t j = s0 + tid + (int64_t)e * kStepThreads;
+            r[e] = (j > s && j < n) ? ld_agent(&rs[j]) : T(0);
+            if (j == l) sh_c = v[e];
+            if (j == s) sh_xs = v[e];
+        }
+        __syncthreads();
+        const T c = sh_c, xs = sh_xs;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t j = s0 + tid + (int64_t)e * kStepThreads;
+            if (j == s)
+                v[e] = c;
+            else if (j > s && j < n)
+                v[e] = fma(-c, r[e], (j == l) ? xs : v[e]);
+        }
+    }
+    // row i is now final: find its pivot, factor it, publish it
+    if (i + 1 > pend) return;
+    int cid[EPT]; // original column ids, all requested before any is used
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s0 + tid + (int64_t)e * kStepThreads;
+        cid[e] = (j >= i && j < n) ? ld_agent(&w.perm[j]) : 0;
+    }
+    PivotKey k = no_candidate();
+    bool bad = false;
+    int cid_i = 0; // original column at position i (thread owning j == i)
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s0 + tid + (int64_t)e * kStepThreads;
+        if (j >= i && j < n && !offer(k, (double)v[e], cid[e], (int)j))
+            bad = true;
+        if (j == i) {
+            sh_vi = v[e];
+            cid_i = cid[e];
+        }
+    }
+    k = block_argmax<kStepThreads>(k, bad, sh, &shflag);
+    const int st = pivot_status(k, bad);
+    const T p = (T)k.value, vi = sh_vi;
+    // publish with device-scope (write-through) stores, wait until every
+    // one is acknowledged, then raise the flag: no cache-wide write-back
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t j = s0 + tid + (int64_t)e * kStepThreads;
+        if (j >= n) continue;
+        T out = v[e];
+        if (st == kStatusOk && j >= i)
+            out = (j == i) ? p : ((j == k.slot) ? vi : v[e]) / p;
+        st_agent(&ri[j], out);
+        if (st == kStatusOk && j == i) { // exchange the column ids
+            st_agent(&w.perm[i], k.colid);
+            st_agent(&w.perm[k.slot], cid_i);
+        }
+    }
+    if (tid == 0) {
+        st_agent(&w.piv_pos[i], k.slot);
+        st_agent(&w.piv_val[i], k.value);
+        if (st != kStatusOk) {
+            st_agent(&w.state->bad_step, (int)i);
+            st_agent(&w.state->status, st);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (tid == 0)
+        __hip_atomic_store(&w.stepflag[i - s0], 1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- single-XCD persistent panel ----
+//
+// The same algorithm as blk_panel, confined to the compute units of one XCD
+// so that the blocks exchange the published rows through that XCD's shared
+// L2: stores are plain (they land in L2), a vmcnt(0) wait orders them before
+// the flag, and readers use loads with the sc0+nt policy, which re-fetch
+// from the L2 even when the line sits in the reader's L1 (measured on
+// gfx950: an sc0-only load keeps returning a stale L1 line, and a plain
+// store is never seen from another XCD by any load policy).
+//
+// The grid is launched eight times over (blocks go to the XCDs in turn);
+// block 0 elects its XCD and the blocks that land there claim slots.  Slot q
+// owns the panel rows s0+1+q, s0+1+q+S, ... (S slots, at most R rows each),
+// all held in registers from the start, so every published row is read once
+// per block and applied to all of its rows: the chain of a step is one flag,
+// one row read, the pivot search and the publication.  All slots must be
+// resident together (S <= 32, one block per compute unit of the XCD); every
+// wait is bounded.
+
+__device__ __forceinline__ int xcc_id()
+{
+    int x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & 0xf;
+}
+
+// L2-served loads (sc0 nt) through a buffer descriptor covering `bytes`
+// from base (out-of-range offsets read as zero).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t l2_rsrc(const void* base,
+                                                         int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                             (int)bytes, 0x00020000);
+}
+
+constexpr int kL2Policy = 3; // cache-policy operand: sc0 | nt
+
+template <typename T>
+__device__ __forceinline__ T l2_load(__amdgpu_buffer_rsrc_t r, int index);
+
+template <>
+__device__ __forceinline__ double l2_load<double>(__amdgpu_buffer_rsrc_t r,
+                                                  int index)
+{
+    return __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(r, index * 8, 0, kL2Policy));
+}
+
+template <>
+__device__ __forceinline__ float l2_load<float>(__amdgpu_buffer_rsrc_t r,
+                                                int index)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(r, index * 4, 0, kL2Policy));
+}
+
+template <>
+__device__ __forceinline__ int l2_load<int>(__amdgpu_buffer_rsrc_t r,
+                                            int index)
+{
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, index * 4, 0, kL2Policy);
+}
+
+// Polling form: the empty asm with a memory clobber keeps the compiler
+// from hoisting or merging the load (the volatile bit of the buffer
+// intrinsics would instead raise the scope to system, past the L2).
+__device__ __forceinline__ int l2_poll(__amdgpu_buffer_rsrc_t r, int index)
+{
+    asm volatile("" ::: "memory");
+    return l2_load<int>(r, index);
+}
+
+// Pivot search and publication of panel row i held in v (single-XCD panel);
+// ids[j - s0] is the original column id at position j.  Thread tid holds
+// positions s0 + e*NT + tid; every position test compares tid with a
+// wave-uniform bound, so no per-entry index lives in a vector register.
+template <typename T, int NT, int EPT>
+__device__ __forceinline__ void panelx_publish(int n, int s0, int i, T (&v)[EPT],
+                                               const int* ids, PivotKey* sh,
+                                               int* shflag, T* sh_vi,
+                                               const BlkWork<T>& w)
+{
+    const int tid = threadIdx.x;
+    T* ri = w.W + (int64_t)i * w.ldw + s0;
+    PivotKey k = no_candidate();
+    bool bad = false;
+    int cid_i = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int base = s0 + e * NT; // position of this entry is base + tid
+        if (tid >= i - base && tid < n - base &&
+            !offer(k, (double)v[e], ids[e * NT + tid], base + tid))
+            bad = true;
+        if (tid == i - base) {
+            *sh_vi = v[e];
+            cid_i = ids[e * NT + tid];
+        }
+    }
+    k = block_argmax<NT>(k, bad, sh, shflag);
+    const int st = pivot_status(k, bad);
+    const T p = (T)k.value, vi = *sh_vi;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int base = s0 + e * NT;
+        if (tid >= n - base) continue;
+        T out = v[e];
+        if (st == kStatusOk && tid >= i - base)
+            out = (tid == i - base) ? p : ((tid == k.slot - base) ? vi : v[e]) / p;
+        ri[e * NT + tid] = out;
+        if (st == kStatusOk && tid == i - base) { // exchange the column ids
+            w.perm[i] = k.colid;
+            w.perm[k.slot] = cid_i;
+        }
+    }
+    if (tid == 0) {
+        w.piv_pos[i] = k.slot;
+        w.piv_val[i] = k.value;
+        if (st != kStatusOk) {
+            w.state->bad_step = i;
+            w.state->status = st;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0); // every store has reached L2
+    __syncthreads();
+    if (tid == 0) w.stepflag[i - s0] = 1;
+}
+
+template <typename T, int NT, int EPT, int R>
+__global__ void __launch_bounds__(NT)
+blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
+{
+    const int n = (int)n64, s0 = (int)s064, pend = (int)pend64;
+    __shared__ PivotKey sh[NT / kWave];
+    __shared__ int shflag, sh_status, sh_slot;
+    __shared__ T sh_c[R], sh_xs[R], sh_vi;
+    __shared__ int sh_perm[NT * EPT]; // column ids of positions s0 ..
+    const int tid = threadIdx.x;
+    // block 0 publishes its XCD (device-coherent store); blocks on other
+    // XCDs leave, the others claim slots from a counter in that XCD's L2
+    if (tid == 0) {
+        const int x = xcc_id();
+        int e = x;
+        if (blockIdx.x == 0) {
+            st_agent(&w.claim[1], x);
+        } else {
+            const uint64_t t0 = now_ticks();
+            while ((e = ld_agent(&w.claim[1])) < 0) {
+                if (now_ticks() - t0 > kWaitTicks) {
+                    st_agent(&w.state->status, (int)kStatusAborted);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        sh_slot = (e == x) ? atomicAdd(&w.claim[0], 1) : -1;
+    }
+    __syncthreads();
+    const int slot = sh_slot;
+    if (slot < 0 || slot >= nslots) return;
+    const __amdgpu_buffer_rsrc_t flags = l2_rsrc(w.stepflag, sizeof(int) * kMaxPanel);
+    const __amdgpu_buffer_rsrc_t pivs = l2_rsrc(w.piv_pos, sizeof(int) * (int64_t)n);
+    const __amdgpu_buffer_rsrc_t stat = l2_rsrc(&w.state->status, sizeof(int));
+    // this block's copy of the column ids, from the snapshot the head step
+    // wrote (the live array changes while the panel runs); every step's
+    // exchange is then applied here as it is observed
+    for (int t = tid; t < n - s0; t += NT) sh_perm[t] = w.perm0[s0 + t];
+    int row[R]; // increasing; -1 once gone
+    int ilast = s0;
+    T v[R][EPT];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        row[q] = s0 + 1 + slot + q * nslots;
+        if (row[q] >= pend) row[q] = -1; // no row
+        else ilast = row[q];
+        if (row[q] < 0) continue;
+        const T* rq = w.W + (int64_t)row[q] * w.ldw;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int j = s0 + tid + e * NT;
+            if (j < n) v[q][e] = rq[j];
+        }
+    }
+    for (int s = s0; s < ilast; ++s) {
+        if (tid == 0) {
+            long spins = 0;
+            const uint64_t t0 = now_ticks();
+            while (s > s0 && l2_poll(flags, s - s0) == 0) {
+                ++spins;
+                if ((spins & 255) == 0) {
+                    if (now_ticks() - t0 > kWaitTicks) {
+                        w.state->status = kStatusAborted;
+                        break;
+                    }
+                    if (l2_poll(stat, 0) != kStatusOk) break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            sh_status = l2_poll(stat, 0);
+        }
+        __syncthreads();
+        if (sh_status != kStatusOk) return; // uniform across the block
+        const int l = __builtin_amdgcn_readfirstlane(l2_load<int>(pivs, s));
+        const T* rs = w.W + (int64_t)s * w.ldw;
+        T r[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) { // one descriptor per entry: the
+            const int base = s0 + e * NT; // bounds check clips at n
+            const int left = n > base ? n - base : 0;
+            r[e] = l2_load<T>(l2_rsrc(rs + base, sizeof(T) * (int64_t)left), tid);
+        }
+        if (tid == 0 && s > s0 && l != s) { // step s exchanged l and s
+            const int a = sh_perm[s - s0];
+            sh_perm[s - s0] = sh_perm[l - s0];
+            sh_perm[l - s0] = a;
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int base = s0 + e * NT;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if (row[q] > s && tid == l - base) sh_c[q] = v[q][e];
+                if (row[q] > s && tid == s - base) sh_xs[q] = v[q][e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (row[q] <= s) continue;
+            const T c = sh_c[q], xs = sh_xs[q];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int base = s0 + e * NT;
+                if (tid == s - base)
+                    v[q][e] = c;
+                else if (tid > s - base && tid < n - base)
+                    v[q][e] = fma(-c, r[e], (tid == l - base) ? xs : v[q][e]);
+            }
+        }
+        // a slot's rows are published in order, so the next one is always
+        // v[0]; afterwards the others move down (one publication to inline)
+        if (row[0] == s + 1) {
+            panelx_publish<T, NT, EPT>(n, s0, s + 1, v[0], sh_perm, sh, &shflag,
+                                       &sh_vi, w);
+#pragma unroll
+            for (int q = 0; q + 1 < R; ++q) {
+                row[q] = row[q + 1];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) v[q][e] = v[q + 1][e];
+            }
+            row[R - 1] = -1;
+        }
+    }
+}
+
+// Panel rows published before the last steps: apply the exchanges of the
+// steps after their own (one wavefront per row; sources found by undoing
+// the exchanges in reverse, every value read before any is written).
+template <typename T>
+__device__ void panel_row_fixup(BlkWork<T>& w, int64_t s0, int nb, int64_t u,
+                                const int* lp)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t pend = s0 + nb;
+    T* row = w.W + u * w.ldw;
+    T val[4];
+    int64_t dst[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = lane + q * kWave; // 0..255: steps u+1.. and their l
+        dst[q] = -1;
+        const int64_t s = u + 1 + (e >> 1);
+        if (s >= pend) continue;
+        const int64_t d = (e & 1) ? lp[s - s0] : s;
+        int64_t pos = d;
+        for (int64_t t = pend - 1; t > u; --t) {
+            const int64_t a = t, b = lp[t - s0];
+            if (pos == a)
+                pos = b;
+            else if (pos == b)
+                pos = a;
+        }
+        if (pos != d) {
+            dst[q] = d;
+            val[q] = row[pos];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (dst[q] >= 0) row[dst[q]] = val[q];
+}
+
 // Elements per thread for a row of `width` active entries, or 0 when the
 // row is wider than the register-resident kernels handle.
 static int step_ept(int64_t width)
@@ -342,6 +812,45 @@ static int step_ept(int64_t width)
     for (int e = 1; e <= 16; e *= 2)
         if (width <= (int64_t)e * kStepThreads) return e;
     return 0;
+}
+
+// Launch the single-XCD panel over rows s0+1 .. pend-1 (NT threads, EPT
+// entries each): R rows per slot, at most 32 slots (one per compute unit of
+// an XCD).  The panel's widths are all within the register-resident head
+// kernel's, which writes the column-id snapshot the panel starts from.
+template <typename T, int NT, int EPT>
+static void launch_panel_x(int64_t n, int64_t s0, int64_t pend,
+                           const BlkWork<T>& w, hipStream_t stream)
+{
+    const int rows = (int)(pend - 1 - s0);
+    const int R = (rows + 31) / 32; // 1 .. 4 (rows <= 127)
+    const int nslots = (rows + R - 1) / R;
+    const dim3 grid((unsigned)(8 * nslots)), block(NT);
+    if (R == 1)
+        hipLaunchKernelGGL((blk_panel_x<T, NT, EPT, 1>), grid, block, 0, stream, n, s0, pend, nslots, w);
+    else if (R == 2)
+        hipLaunchKernelGGL((blk_panel_x<T, NT, EPT, 2>), grid, block, 0, stream, n, s0, pend, nslots, w);
+    else if (R == 3)
+        hipLaunchKernelGGL((blk_panel_x<T, NT, EPT, 3>), grid, block, 0, stream, n, s0, pend, nslots, w);
+    else
+        hipLaunchKernelGGL((blk_panel_x<T, NT, EPT, 4>), grid, block, 0, stream, n, s0, pend, nslots, w);
+}
+
+// Single-XCD panel for a row width; false when wider than it handles
+// (4 rows of up to 11 entries per thread keep every slot's rows in
+// registers).
+template <typename T>
+static bool try_panel_x(int64_t n, int64_t s0, int64_t pend,
+                        const BlkWork<T>& w, hipStream_t stream)
+{
+    const int64_t width = n - s0;
+    if (width <= 512) launch_panel_x<T, 512, 1>(n, s0, pend, w, stream);
+    else if (width <= 1024) launch_panel_x<T, 512, 2>(n, s0, pend, w, stream);
+    else if (width <= 2048) launch_panel_x<T, 512, 4>(n, s0, pend, w, stream);
+    else if (width <= 4096) launch_panel_x<T, 512, 8>(n, s0, pend, w, stream);
+    else if (width <= 768 * 11) launch_panel_x<T, 768, 11>(n, s0, pend, w, stream);
+    else return false;
+    return true;
 }
 
 template <typename T>
@@ -387,6 +896,24 @@ static void launch_step(int64_t n, int64_t s, int64_t s0, int64_t pend,
 // The same block also inverts the 16 x 16 diagonal blocks of the unit upper
 // triangle U11 of the factored panel (back substitution, one column per
 // thread), for the triangular solve below.
+template <typename T>
+__device__ void panel_row_fixup(BlkWork<T>& w, int64_t s0, int nb, int64_t u,
+                                const int* lp);
+
+// Fix-up of the panel rows published by the persistent panel kernel (four
+// rows per block).  Runs before blk_perm, which reads the fixed rows (U11).
+template <typename T>
+__global__ void __launch_bounds__(kBlkThreads)
+blk_fixup(int64_t s0, int nb, BlkWork<T> w)
+{
+    __shared__ int lp[kMaxPanel];
+    if (w.state->status != kStatusOk) return;
+    for (int t = threadIdx.x; t < nb; t += kBlkThreads) lp[t] = w.piv_pos[s0 + t];
+    __syncthreads();
+    const int64_t u = s0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u < s0 + nb - 1) panel_row_fixup(w, s0, nb, u, lp);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlkThreads)
 blk_perm(int64_t s0, int nb, BlkWork<T> w)
@@ -580,7 +1107,8 @@ blk_finalize(int64_t n, const int* __restrict__ piv_pos,
             out->logabsdet = sing ? -INFINITY : NAN;
             out->sign = 0.0;
             out->info = sing ? (int64_t)state->bad_step + 1
-                             : (int64_t)MC_INFO_NONFINITE;
+                             : (st == kStatusAborted ? (int64_t)MC_INFO_ABORTED
+                                                     : (int64_t)MC_INFO_NONFINITE);
         }
         return;
     }
@@ -645,8 +1173,26 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         const int nb = (int)std::min<int64_t>(b, n - s0);
         const int64_t pend = s0 + nb;
         launch_head<T>(n, s0, w, stream);
-        for (int64_t s = s0; s < pend; ++s)
-            launch_step<T>(n, s, s0, pend, w, stream);
+        const int ept = step_ept(n - s0);
+        const bool persistent = ept > 0 && nb > 1;
+        if (persistent && !try_panel_x<T>(n, s0, pend, w, stream)) {
+            switch (ept) { // wider than the single-XCD panel: across XCDs
+#define MC_PANEL(E)                                                           \
+    case E:                                                                   \
+        hipLaunchKernelGGL((blk_panel<T, E>), dim3((unsigned)(nb - 1)),       \
+                           dim3(kStepThreads), 0, stream, n, s0, pend, w);    \
+        break;
+                MC_PANEL(1) MC_PANEL(2) MC_PANEL(4) MC_PANEL(8) MC_PANEL(16)
+#undef MC_PANEL
+            }
+        } else if (!persistent) {
+            for (int64_t s = s0; s < pend; ++s)
+                launch_step<T>(n, s, s0, pend, w, stream);
+        }
+        const int fix = persistent ? 1 : 0;
+        if (fix) // rows published early: the later steps' exchanges
+            hipLaunchKernelGGL(blk_fixup<T>, dim3((unsigned)((nb + 3) / 4)),
+                               dim3(kBlkThreads), 0, stream, s0, nb, w);
         if (pend >= n) break;
         const int64_t rows = n - pend;
         hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,

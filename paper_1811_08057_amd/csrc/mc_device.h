@@ -16,7 +16,12 @@ namespace mc {
 constexpr int kWave = 64;
 
 // Status codes kept in device memory by a running factorisation.
-enum : int { kStatusOk = 0, kStatusSingular = 1, kStatusNonfinite = 2 };
+enum : int {
+    kStatusOk = 0,
+    kStatusSingular = 1,
+    kStatusNonfinite = 2,
+    kStatusAborted = 3 // a bounded inter-block wait ran out (never expected)
+};
 
 struct PivotKey {
     double absval; // |value|, -1 for "no candidate"

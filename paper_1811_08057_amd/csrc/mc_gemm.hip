@@ -20,53 +20,64 @@ constexpr int kGemmThreads = 256;
 
 // ---------------------------------------------------------------------------
 // FP64 / FP32: one scalar operand per lane, K = 4 per instruction.  The
+// block is WGM x WGN wavefronts, each owning TM x TN tiles of 16 x 16.  The
 // K loop is double-buffered: chunk c+1 is read from global memory into
 // registers while chunk c feeds the matrix cores, then parked in the other
-// LDS buffer; one barrier per chunk.
-// (two blocks per CU: the register budget then covers the 64 FP64
-// accumulators of a 4 x 4 wave tile without spilling)
-template <class P, int WT>
-__global__ void __launch_bounds__(kGemmThreads, 2)
+// LDS buffer; one barrier per chunk.  (The FP64 matrix cores reach their
+// peak only with two or more wavefronts issuing per SIMD, hence 8-wave
+// blocks for the large tile.)
+template <class P, int WGM, int WGN, int TM, int TN>
+__global__ void __launch_bounds__(64 * WGM * WGN, 2)
 gemm_scalar(GemmArgs<typename P::T> g)
 {
     using T = typename P::T;
-    constexpr int BT = 32 * WT;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int BM = 16 * TM * WGM, BN = 16 * TN * WGN;
     constexpr int KC = 16;
-    constexpr int LDS_LD = BT + 16;               // conflict-free fragment reads
-    constexpr int PE = BT * KC / kGemmThreads;    // elements per thread per chunk
-    __shared__ T As[2][KC][LDS_LD];               // -L, transposed (k major)
-    __shared__ T Bs[2][KC][LDS_LD];               // U
+    constexpr int LDA = BM + 16, LDB = BN + 16; // conflict-free fragment reads
+    constexpr int PA = (BM * KC + NT - 1) / NT, PB = (BN * KC + NT - 1) / NT;
+    __shared__ T As[2][KC][LDA]; // -L, transposed (k major)
+    __shared__ T Bs[2][KC][LDB]; // U
     if (g.state->status != kStatusOk) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wm = wid >> 1, wn = wid & 1;
-    const int64_t rb = (int64_t)blockIdx.y * BT, cb = (int64_t)blockIdx.x * BT;
+    const int wm = wid / WGN, wn = wid % WGN;
+    const int64_t rb = (int64_t)blockIdx.y * BM, cb = (int64_t)blockIdx.x * BN;
     const int col_in = lane & 15, kq_lane = lane >> 4;
 
-    T pa[PE], pb[PE];
+    T pa[PA], pb[PB];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int p = 0; p < PE; ++p) {
-            const int e = tid + p * kGemmThreads;
+        for (int p = 0; p < PA; ++p) {
+            const int e = tid + p * NT;
             const int rr = e / KC, kk = e - rr * KC;
             const int64_t row = rb + rr;
-            pa[p] = (row < g.M && k0 + kk < g.K) ? -g.L[row * g.ldl + k0 + kk]
-                                                 : T(0);
-            const int kb = e / BT, cc = e - kb * BT;
+            pa[p] = (e < BM * KC && row < g.M && k0 + kk < g.K)
+                        ? -g.L[row * g.ldl + k0 + kk]
+                        : T(0);
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int e = tid + p * NT;
+            const int kb = e / BN, cc = e - kb * BN;
             const int64_t col = cb + cc;
-            pb[p] = (col < g.N && k0 + kb < g.K)
+            pb[p] = (e < BN * KC && col < g.N && k0 + kb < g.K)
                         ? g.U[(int64_t)(k0 + kb) * g.ldu + g.c0 + col]
                         : T(0);
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < PE; ++p) {
-            const int e = tid + p * kGemmThreads;
+        for (int p = 0; p < PA; ++p) {
+            const int e = tid + p * NT;
             const int rr = e / KC, kk = e - rr * KC;
-            As[buf][kk][rr] = pa[p];
-            const int kb = e / BT, cc = e - kb * BT;
-            Bs[buf][kb][cc] = pb[p];
+            if (e < BM * KC) As[buf][kk][rr] = pa[p];
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int e = tid + p * NT;
+            const int kb = e / BN, cc = e - kb * BN;
+            if (e < BN * KC) Bs[buf][kb][cc] = pb[p];
         }
     };
 
@@ -74,11 +85,11 @@ gemm_scalar(GemmArgs<typename P::T> g)
 
     // the product -L U accumulates from zero; C joins it in the epilogue, so
     // the K loop holds only accumulators, operands and the prefetch
-    typename P::Acc acc[WT][WT];
+    typename P::Acc acc[TM][TN];
 #pragma unroll
-    for (int ti = 0; ti < WT; ++ti)
+    for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj)
+        for (int tj = 0; tj < TN; ++tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[ti][tj][r] = T(0);
 
@@ -90,16 +101,17 @@ gemm_scalar(GemmArgs<typename P::T> g)
         if (c + 1 < nch) gload((c + 1) * KC);
 #pragma unroll
         for (int kq = 0; kq < KC; kq += 4) {
-            T a[WT], b[WT];
+            T a[TM], b[TN];
 #pragma unroll
-            for (int t = 0; t < WT; ++t) {
-                a[t] = As[buf][kq + kq_lane][wm * 16 * WT + t * 16 + col_in];
-                b[t] = Bs[buf][kq + kq_lane][wn * 16 * WT + t * 16 + col_in];
-            }
+            for (int t = 0; t < TM; ++t)
+                a[t] = As[buf][kq + kq_lane][wm * 16 * TM + t * 16 + col_in];
 #pragma unroll
-            for (int ti = 0; ti < WT; ++ti)
+            for (int t = 0; t < TN; ++t)
+                b[t] = Bs[buf][kq + kq_lane][wn * 16 * TN + t * 16 + col_in];
 #pragma unroll
-                for (int tj = 0; tj < WT; ++tj)
+            for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TN; ++tj)
                     acc[ti][tj] = P::mma(a[ti], b[tj], acc[ti][tj]);
         }
         if (c + 1 < nch) sstore(buf ^ 1);
@@ -110,15 +122,15 @@ gemm_scalar(GemmArgs<typename P::T> g)
     // column range, which no block writes; otherwise src == dst and the
     // same thread reads before it writes.
 #pragma unroll
-    for (int tj = 0; tj < WT; ++tj) {
-        const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
+    for (int tj = 0; tj < TN; ++tj) {
+        const int64_t col = cb + wn * 16 * TN + tj * 16 + col_in;
         if (col >= g.N) continue;
         const int64_t src = g.colsrc[g.c0 + col];
 #pragma unroll
-        for (int ti = 0; ti < WT; ++ti)
+        for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = rb + wm * 16 * WT + ti * 16 + P::drow(lane, r);
+                const int64_t row = rb + wm * 16 * TM + ti * 16 + P::drow(lane, r);
                 if (row < g.M) {
                     T* crow = g.C + (g.r0 + row) * g.ldc;
                     crow[g.c0 + col] = crow[src] + acc[ti][tj][r];
@@ -225,19 +237,17 @@ gemm_bf16x3(GemmArgs<float> g)
 // ---------------------------------------------------------------------------
 
 // Large tiles while they still give every CU work; smaller ones after.
-static int pick_wt(int64_t M, int64_t N)
+static bool big_tiles(int64_t M, int64_t N)
 {
-    const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
-    return big >= 512 ? 4 : 2;
+    return ((M + 127) / 128) * ((N + 127) / 128) >= 512;
 }
 
-template <int WT, class Kern, class Args>
-static void launch_tiles(Kern k, const Args& g, hipStream_t stream)
+template <class Kern, class Args>
+static void launch_grid(Kern k, const Args& g, int bm, int bn, int threads,
+                        hipStream_t stream)
 {
-    constexpr int BT = 32 * WT;
-    const dim3 grid((unsigned)((g.N + BT - 1) / BT),
-                    (unsigned)((g.M + BT - 1) / BT));
-    hipLaunchKernelGGL(k, grid, dim3(kGemmThreads), 0, stream, g);
+    const dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + bm - 1) / bm));
+    hipLaunchKernelGGL(k, grid, dim3(threads), 0, stream, g);
 }
 
 template <>
@@ -245,10 +255,10 @@ hipError_t launch_trailing_update<double>(const GemmArgs<double>& g,
                                           int update, hipStream_t stream)
 {
     if (update != MC_UPDATE_NATIVE) return hipErrorInvalidValue;
-    if (pick_wt(g.M, g.N) == 4)
-        launch_tiles<4>(gemm_scalar<MfmaF64, 4>, g, stream);
-    else
-        launch_tiles<2>(gemm_scalar<MfmaF64, 2>, g, stream);
+    if (big_tiles(g.M, g.N)) // 8 waves (2 x 4), 64 x 32 per wave: 128 x 128
+        launch_grid((gemm_scalar<MfmaF64, 2, 4, 4, 2>), g, 128, 128, 512, stream);
+    else // 4 waves (2 x 2), 32 x 32 per wave: 64 x 64
+        launch_grid((gemm_scalar<MfmaF64, 2, 2, 2, 2>), g, 64, 64, 256, stream);
     return hipGetLastError();
 }
 
@@ -256,17 +266,17 @@ template <>
 hipError_t launch_trailing_update<float>(const GemmArgs<float>& g, int update,
                                          hipStream_t stream)
 {
-    const bool big = pick_wt(g.M, g.N) == 4;
+    const bool big = big_tiles(g.M, g.N);
     if (update == MC_UPDATE_BF16X3) {
         if (big)
-            launch_tiles<4>(gemm_bf16x3<4>, g, stream);
+            launch_grid(gemm_bf16x3<4>, g, 128, 128, 256, stream);
         else
-            launch_tiles<2>(gemm_bf16x3<2>, g, stream);
+            launch_grid(gemm_bf16x3<2>, g, 64, 64, 256, stream);
     } else {
         if (big)
-            launch_tiles<4>(gemm_scalar<MfmaF32, 4>, g, stream);
+            launch_grid((gemm_scalar<MfmaF32, 2, 4, 4, 2>), g, 128, 128, 512, stream);
         else
-            launch_tiles<2>(gemm_scalar<MfmaF32, 2>, g, stream);
+            launch_grid((gemm_scalar<MfmaF32, 2, 2, 2, 2>), g, 64, 64, 256, stream);
     }
     return hipGetLastError();
 }

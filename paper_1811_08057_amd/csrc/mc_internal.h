@@ -43,10 +43,13 @@ struct BlkWork {
     int* piv_pos;  // position of each step's pivot in its row (>= step)
     double* piv_val;
     int* perm;     // perm[pos] = original column now at position pos
+    int* perm0;    // perm as the panel's first step left it (single-XCD panel)
     int* colsrc;   // source position of each trailing destination position
     int* srcp;     // source position of each panel column s0 + t
     int* moved;    // trailing positions remapped by the previous panel
     T* dinv;       // inverses of the 16 x 16 diagonal blocks of U11
+    int* stepflag; // per panel step: 1 once its pivot row is published
+    int* claim;    // single-XCD panel kernel: [0] row-claim counter, [1] elected XCD
     DevState* state;
 };
 
