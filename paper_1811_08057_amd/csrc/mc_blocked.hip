@@ -585,59 +585,159 @@ __device__ __forceinline__ int l2_poll(__amdgpu_buffer_rsrc_t r, int index)
     return l2_load<int>(r, index);
 }
 
-// Pivot search and publication of panel row i held in v (single-XCD panel);
-// ids[j - s0] is the original column id at position j.  Thread tid holds
-// positions s0 + e*NT + tid; every position test compares tid with a
-// wave-uniform bound, so no per-entry index lives in a vector register.
+// Scratch of the single-XCD panel's pivot search (one entry per wavefront).
+struct PanelXShared {
+    double wmax[16];
+    int wbad[16];
+    unsigned long long wkey[16];
+};
+
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long x)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const unsigned long long y = __shfl_xor(x, off, kWave);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// Entry e (wave-uniform, < EPT) of a register array, for the one thread
+// that owns a given position: a chain of selects that starts from a
+// constant (a select between two array loads could be folded into one
+// load at a computed address, which would move the array to scratch).
+template <typename T, int EPT>
+__device__ __forceinline__ T pick(const T (&a)[EPT], int e)
+{
+    T r = T(0);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) r = (q == e) ? a[q] : r;
+    return r;
+}
+
+template <typename T, int EPT>
+__device__ __forceinline__ void put(T (&a)[EPT], int e, T v)
+{
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) a[q] = (q == e) ? v : a[q];
+}
+
+// Update of one panel row x by step s (pivot position l): every entry right
+// of s takes -c times the factored pivot row, the row's entry at l (the
+// multiplier c) is stashed at s (Figure 6, step 4.8) and position l takes
+// the row's old entry at s, xs, minus c times the pivot row's entry there.
+// r holds the pivot row with zeros at positions <= s and >= n, so one fma
+// per entry does the bulk; the threads owning s and l then set those two.
+// The pivot row arrives unfactored (entries v_j, pivot p): cp = c / p, and
+// the factored entry at l is the pivot row's entry at s (atl); the panel's
+// first row arrives factored: cp = c, atl = its entry at l.
 template <typename T, int NT, int EPT>
-__device__ __forceinline__ void panelx_publish(int n, int s0, int i, T (&v)[EPT],
-                                               const int* ids, PivotKey* sh,
-                                               int* shflag, T* sh_vi,
-                                               const BlkWork<T>& w)
+__device__ __forceinline__ void panelx_apply(T (&x)[EPT], const T (&r)[EPT],
+                                             int s0, int s, int l, T c, T cp,
+                                             T xs, bool factored, T vs)
 {
     const int tid = threadIdx.x;
-    T* ri = w.W + (int64_t)i * w.ldw + s0;
-    PivotKey k = no_candidate();
-    bool bad = false;
-    int cid_i = 0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int base = s0 + e * NT; // position of this entry is base + tid
-        if (tid >= i - base && tid < n - base &&
-            !offer(k, (double)v[e], ids[e * NT + tid], base + tid))
-            bad = true;
-        if (tid == i - base) {
-            *sh_vi = v[e];
-            cid_i = ids[e * NT + tid];
-        }
+    for (int e = 0; e < EPT; ++e) x[e] = fma(-cp, r[e], x[e]);
+    if (tid == (l - s0) % NT) { // owner of position l (l >= s)
+        const int el = (l - s0) / NT;
+        put<T, EPT>(x, el, fma(-cp, factored ? pick<T, EPT>(r, el) : vs, xs));
     }
-    k = block_argmax<NT>(k, bad, sh, shflag);
-    const int st = pivot_status(k, bad);
-    const T p = (T)k.value, vi = *sh_vi;
+    if (tid == (s - s0) % NT) put<T, EPT>(x, (s - s0) / NT, c);
+}
+
+// Publication of panel row i held in v (single-XCD panel): the row goes out
+// unfactored first (the stores drain while the pivot is searched), then the
+// pivot (largest |v| over positions >= i, ties to the smallest original
+// column id, Section 2.2), the column-id exchange, and the flag, which
+// carries the pivot position + 1.  ids[j - s0] is the original column id at
+// position j.  Thread tid holds positions s0 + e*NT + tid; position tests
+// compare tid with wave-uniform bounds, so no per-entry index is kept in a
+// vector register (n <= 2^30: 32-bit indices).
+template <typename T, int NT, int EPT>
+__device__ __forceinline__ void panelx_publish(int n, int s0, int i, const T (&v)[EPT],
+                                               const int* ids, PanelXShared& sm,
+                                               const BlkWork<T>& w)
+{
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    T* ri = w.W + (int64_t)i * w.ldw + s0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+        if (tid < n - s0 - e * NT) ri[e * NT + tid] = v[e];
+    // pass 1: the largest |v| and whether any entry is not finite
+    double m = 0.0;
+    bool bad = false;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int base = s0 + e * NT;
-        if (tid >= n - base) continue;
-        T out = v[e];
-        if (st == kStatusOk && tid >= i - base)
-            out = (tid == i - base) ? p : ((tid == k.slot - base) ? vi : v[e]) / p;
-        ri[e * NT + tid] = out;
-        if (st == kStatusOk && tid == i - base) { // exchange the column ids
-            w.perm[i] = k.colid;
-            w.perm[k.slot] = cid_i;
-        }
+        const bool in = tid >= i - base && tid < n - base;
+        const double a = fabs((double)v[e]);
+        bad |= in && !isfinite(a);
+        m = fmax(m, in ? a : 0.0);
     }
-    if (tid == 0) {
-        w.piv_pos[i] = k.slot;
-        w.piv_val[i] = k.value;
-        if (st != kStatusOk) {
-            w.state->bad_step = i;
-            w.state->status = st;
+    m = wave_max(m);
+    const bool wbad = __any(bad);
+    if (lane == 0) {
+        sm.wmax[wv] = m;
+        sm.wbad[wv] = wbad;
+    }
+    __syncthreads();
+    double M = sm.wmax[0];
+    int anybad = sm.wbad[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+        M = fmax(M, sm.wmax[q]);
+        anybad |= sm.wbad[q];
+    }
+    const int st = anybad ? kStatusNonfinite : (M > 0.0 ? kStatusOk : kStatusSingular);
+    if (st == kStatusOk) { // uniform
+        // pass 2: among the entries of magnitude M, the smallest column id;
+        // key = id << 32 | sign << 31 | slot
+        unsigned long long key = ~0ull;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int base = s0 + e * NT;
+            if (tid >= i - base && tid < n - base && fabs((double)v[e]) == M) {
+                const unsigned long long c =
+                    ((unsigned long long)(unsigned)ids[e * NT + tid] << 32) |
+                    ((unsigned long long)(v[e] < T(0)) << 31) |
+                    (unsigned long long)(unsigned)(base + tid);
+                key = c < key ? c : key;
+            }
         }
+        key = wave_min(key);
+        if (lane == 0) sm.wkey[wv] = key;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long k = sm.wkey[0];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) k = sm.wkey[q] < k ? sm.wkey[q] : k;
+            const int slot = (int)(k & 0x7fffffffu);
+            const int colid = (int)(k >> 32);
+            w.piv_pos[i] = slot;
+            w.piv_val[i] = ((k >> 31) & 1u) ? -M : M;
+            w.perm[slot] = ids[i - s0]; // exchange the column ids
+            w.perm[i] = colid;
+            sm.wkey[0] = (unsigned long long)(slot + 1);
+        }
+    } else if (tid == 0) {
+        w.piv_pos[i] = -1;
+        w.piv_val[i] = 0.0;
+        w.state->bad_step = i;
+        w.state->status = st;
+        sm.wkey[0] = 1;
     }
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0); // every store has reached L2
     __syncthreads();
-    if (tid == 0) w.stepflag[i - s0] = 1;
+    if (tid == 0) w.stepflag[i - s0] = (int)sm.wkey[0];
 }
 
 template <typename T, int NT, int EPT, int R>
@@ -645,9 +745,9 @@ __global__ void __launch_bounds__(NT)
 blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
 {
     const int n = (int)n64, s0 = (int)s064, pend = (int)pend64;
-    __shared__ PivotKey sh[NT / kWave];
-    __shared__ int shflag, sh_status, sh_slot;
-    __shared__ T sh_c[R], sh_xs[R], sh_vi;
+    __shared__ PanelXShared sm;
+    __shared__ int sh_status, sh_slot, sh_l;
+    __shared__ T sh_c[R], sh_xs[R];
     __shared__ int sh_perm[NT * EPT]; // column ids of positions s0 ..
     const int tid = threadIdx.x;
     // block 0 publishes its XCD (device-coherent store); blocks on other
@@ -674,6 +774,7 @@ blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
     if (slot < 0 || slot >= nslots) return;
     const __amdgpu_buffer_rsrc_t flags = l2_rsrc(w.stepflag, sizeof(int) * kMaxPanel);
     const __amdgpu_buffer_rsrc_t pivs = l2_rsrc(w.piv_pos, sizeof(int) * (int64_t)n);
+    const __amdgpu_buffer_rsrc_t pvals = l2_rsrc(w.piv_val, sizeof(double) * (int64_t)n);
     const __amdgpu_buffer_rsrc_t stat = l2_rsrc(&w.state->status, sizeof(int));
     // this block's copy of the column ids, from the snapshot the head step
     // wrote (the live array changes while the panel runs); every step's
@@ -687,75 +788,83 @@ blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
         row[q] = s0 + 1 + slot + q * nslots;
         if (row[q] >= pend) row[q] = -1; // no row
         else ilast = row[q];
-        if (row[q] < 0) continue;
-        const T* rq = w.W + (int64_t)row[q] * w.ldw;
+        const T* rq = w.W + (int64_t)(row[q] < 0 ? 0 : row[q]) * w.ldw + s0;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int j = s0 + tid + e * NT;
-            if (j < n) v[q][e] = rq[j];
-        }
+        for (int e = 0; e < EPT; ++e)
+            v[q][e] = (row[q] >= 0 && tid < n - s0 - e * NT) ? rq[e * NT + tid] : T(0);
     }
     for (int s = s0; s < ilast; ++s) {
         if (tid == 0) {
-            long spins = 0;
-            const uint64_t t0 = now_ticks();
-            while (s > s0 && l2_poll(flags, s - s0) == 0) {
-                ++spins;
-                if ((spins & 255) == 0) {
-                    if (now_ticks() - t0 > kWaitTicks) {
-                        w.state->status = kStatusAborted;
-                        break;
+            int f = 1;
+            if (s > s0) {
+                long spins = 0;
+                const uint64_t t0 = now_ticks();
+                while ((f = l2_poll(flags, s - s0)) == 0) {
+                    ++spins;
+                    if ((spins & 255) == 0) {
+                        if (now_ticks() - t0 > kWaitTicks) {
+                            w.state->status = kStatusAborted;
+                            break;
+                        }
+                        if (l2_poll(stat, 0) != kStatusOk) break;
                     }
-                    if (l2_poll(stat, 0) != kStatusOk) break;
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                __builtin_amdgcn_s_sleep(1);
             }
             sh_status = l2_poll(stat, 0);
+            sh_l = (s > s0) ? f - 1 : l2_load<int>(pivs, s);
         }
         __syncthreads();
         if (sh_status != kStatusOk) return; // uniform across the block
-        const int l = __builtin_amdgcn_readfirstlane(l2_load<int>(pivs, s));
+        const int l = __builtin_amdgcn_readfirstlane(sh_l);
+        const bool factored = (s == s0); // the head step's row is factored
         const T* rs = w.W + (int64_t)s * w.ldw;
+        // the pivot row through a descriptor that starts at position s+1:
+        // offsets below it wrap to huge values and, like those at or past
+        // n, fail the range check and read as zero
+        const __amdgpu_buffer_rsrc_t rrow =
+            l2_rsrc(rs + s + 1, sizeof(T) * (int64_t)(n - s - 1));
         T r[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) { // one descriptor per entry: the
-            const int base = s0 + e * NT; // bounds check clips at n
-            const int left = n > base ? n - base : 0;
-            r[e] = l2_load<T>(l2_rsrc(rs + base, sizeof(T) * (int64_t)left), tid);
+        for (int e = 0; e < EPT; ++e) r[e] = l2_load<T>(rrow, s0 + e * NT + tid - s - 1);
+        T vs = T(0), ps = T(1);
+        if (!factored) {
+            vs = l2_load<T>(l2_rsrc(rs + s, sizeof(T)), 0);
+            ps = (T)l2_load<double>(pvals, s);
         }
-        if (tid == 0 && s > s0 && l != s) { // step s exchanged l and s
+        if (tid == 0 && !factored && l != s) { // step s exchanged l and s
             const int a = sh_perm[s - s0];
             sh_perm[s - s0] = sh_perm[l - s0];
             sh_perm[l - s0] = a;
         }
+        if (tid == (l - s0) % NT) { // owner of position l: the multipliers
+            const int el = (l - s0) / NT;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int base = s0 + e * NT;
+            for (int q = 0; q < R; ++q) sh_c[q] = pick<T, EPT>(v[q], el);
+        }
+        if (tid == (s - s0) % NT) { // owner of position s: the entries at s
+            const int es = (s - s0) / NT;
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                if (row[q] > s && tid == l - base) sh_c[q] = v[q][e];
-                if (row[q] > s && tid == s - base) sh_xs[q] = v[q][e];
-            }
+            for (int q = 0; q < R; ++q) sh_xs[q] = pick<T, EPT>(v[q], es);
         }
         __syncthreads();
+        // the row to publish next is always v[0] (a slot's rows go out in
+        // order): update it, publish it, then update the others
+        const bool pub = (row[0] == s + 1);
+        if (pub) {
+            const T c = sh_c[0];
+            panelx_apply<T, NT, EPT>(v[0], r, s0, s, l, c, factored ? c : c / ps,
+                                     sh_xs[0], factored, vs);
+            panelx_publish<T, NT, EPT>(n, s0, s + 1, v[0], sh_perm, sm, w);
+        }
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            if (row[q] <= s) continue;
-            const T c = sh_c[q], xs = sh_xs[q];
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int base = s0 + e * NT;
-                if (tid == s - base)
-                    v[q][e] = c;
-                else if (tid > s - base && tid < n - base)
-                    v[q][e] = fma(-c, r[e], (tid == l - base) ? xs : v[q][e]);
-            }
+            if (row[q] <= s || (q == 0 && pub)) continue;
+            const T c = sh_c[q];
+            panelx_apply<T, NT, EPT>(v[q], r, s0, s, l, c, factored ? c : c / ps,
+                                     sh_xs[q], factored, vs);
         }
-        // a slot's rows are published in order, so the next one is always
-        // v[0]; afterwards the others move down (one publication to inline)
-        if (row[0] == s + 1) {
-            panelx_publish<T, NT, EPT>(n, s0, s + 1, v[0], sh_perm, sh, &shflag,
-                                       &sh_vi, w);
+        if (pub) {
 #pragma unroll
             for (int q = 0; q + 1 < R; ++q) {
                 row[q] = row[q + 1];
@@ -912,6 +1021,33 @@ blk_fixup(int64_t s0, int nb, BlkWork<T> w)
     __syncthreads();
     const int64_t u = s0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (u < s0 + nb - 1) panel_row_fixup(w, s0, nb, u, lp);
+}
+
+// Fix-up after the single-XCD panel, one block per panel row u: rows after
+// the first were published unfactored, so factor them in place (row u of
+// Section 2.3 divided by its pivot, whose slot takes the entry at u; the
+// multipliers left of u stay), then apply the later steps' exchanges.
+template <typename T>
+__global__ void __launch_bounds__(kBlkThreads)
+blk_fixup_x(int64_t n, int64_t s0, int nb, BlkWork<T> w)
+{
+    __shared__ int lp[kMaxPanel];
+    if (w.state->status != kStatusOk) return;
+    for (int t = threadIdx.x; t < nb; t += kBlkThreads) lp[t] = w.piv_pos[s0 + t];
+    const int64_t u = s0 + blockIdx.x;
+    if (u > s0) {
+        T* row = w.W + u * w.ldw;
+        const T p = (T)w.piv_val[u];
+        const int64_t l = w.piv_pos[u];
+        const T vu = row[u];
+        __syncthreads(); // every thread has vu before position u is written
+        for (int64_t j = u + threadIdx.x; j < n; j += kBlkThreads) {
+            const T x = row[j];
+            row[j] = (j == u) ? p : ((j == l) ? vu : x) / p;
+        }
+    }
+    __syncthreads(); // the factored row (and lp) is visible to the block
+    if (u < s0 + nb - 1 && threadIdx.x < kWave) panel_row_fixup(w, s0, nb, u, lp);
 }
 
 template <typename T>
@@ -1175,7 +1311,8 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         launch_head<T>(n, s0, w, stream);
         const int ept = step_ept(n - s0);
         const bool persistent = ept > 0 && nb > 1;
-        if (persistent && !try_panel_x<T>(n, s0, pend, w, stream)) {
+        const bool single_xcd = persistent && try_panel_x<T>(n, s0, pend, w, stream);
+        if (persistent && !single_xcd) {
             switch (ept) { // wider than the single-XCD panel: across XCDs
 #define MC_PANEL(E)                                                           \
     case E:                                                                   \
@@ -1189,8 +1326,10 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
             for (int64_t s = s0; s < pend; ++s)
                 launch_step<T>(n, s, s0, pend, w, stream);
         }
-        const int fix = persistent ? 1 : 0;
-        if (fix) // rows published early: the later steps' exchanges
+        if (single_xcd) // unfactored rows; the later steps' exchanges
+            hipLaunchKernelGGL(blk_fixup_x<T>, dim3((unsigned)nb),
+                               dim3(kBlkThreads), 0, stream, n, s0, nb, w);
+        else if (persistent) // rows published early: later exchanges
             hipLaunchKernelGGL(blk_fixup<T>, dim3((unsigned)((nb + 3) / 4)),
                                dim3(kBlkThreads), 0, stream, s0, nb, w);
         if (pend >= n) break;
