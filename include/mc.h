@@ -212,6 +212,20 @@ mc_status mc_autotune_batched(int dtype, int update, int64_t n_max_tune,
                               void* work, size_t work_bytes, void* stream);
 
 /*
+ * Blocked path scheduling.  With lookahead on (the default), each panel's
+ * trailing update is split: the rows of the next panel are updated on the
+ * caller's stream, the remaining rows on a second stream the library owns
+ * (one per device, default priority), where that update runs beside the
+ * next panel's factorisation; the caller's stream waits for it (an event)
+ * before the next triangular solve and before the call's last kernel, so
+ * from the caller's side the call is still ordered on its stream (and can
+ * be captured into a graph).  Off: every kernel runs on the caller's
+ * stream.  Returns the previous setting (1 on, 0 off).  Process-wide;
+ * calls that enqueue blocked work are serialised on a lock while they do.
+ */
+int mc_lookahead_enable(int on);
+
+/*
  * Optional timing of the kernel that dominates a call: the condensation
  * update of the plain path (timed as the whole run of per-step launches).
  * While enabled, each call records a pair of HIP events on its stream

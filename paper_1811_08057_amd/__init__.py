@@ -36,7 +36,7 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_tune_set", "mc_autotune_workspace", "mc_autotune_batched",
            "mc_last_hip_error", "mc_logdet_factor_workspace",
            "mc_logdet_factor", "mc_logdet_backward_workspace",
-           "mc_logdet_backward")
+           "mc_logdet_backward", "mc_lookahead_enable")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
                             vp, sz, vp]
     L.mc_logdet.restype = ctypes.c_int
     dp = ctypes.POINTER(ctypes.c_double)
+    L.mc_lookahead_enable.argtypes = [ctypes.c_int]
+    L.mc_lookahead_enable.restype = ctypes.c_int
     L.mc_profile_enable.argtypes = [ctypes.c_int]
     L.mc_profile_enable.restype = ctypes.c_int
     L.mc_profile_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), dp, dp]
@@ -201,6 +203,13 @@ class Profile(NamedTuple):
     launches: int
     alg_bytes: float
     alg_flops: float
+
+
+def lookahead_enable(on: bool = True) -> bool:
+    """Split each blocked trailing update across two streams (the default)
+    or keep every kernel on the caller's stream; returns the previous
+    setting."""
+    return bool(lib().mc_lookahead_enable(1 if on else 0))
 
 
 def profile_enable(on: bool = True) -> None:

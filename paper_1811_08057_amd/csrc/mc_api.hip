@@ -144,8 +144,8 @@ static size_t blocked_bytes(int64_t n, int dtype, int64_t b, bool with_w)
     t += align_up(elem * (size_t)n * (size_t)b, kAlign);       // L
     t += align_up(sizeof(int) * (size_t)n, kAlign);            // piv_pos
     t += align_up(sizeof(double) * (size_t)n, kAlign);         // piv_val
-    t += 3 * align_up(sizeof(int) * (size_t)n, kAlign);        // perm, perm0, colsrc
-    t += 2 * align_up(sizeof(int) * (size_t)kMaxPanel, kAlign); // srcp, moved
+    t += 4 * align_up(sizeof(int) * (size_t)n, kAlign);        // perm, perm0, colsrc x2
+    t += 4 * align_up(sizeof(int) * (size_t)kMaxPanel, kAlign); // srcp, moved x2
     t += align_up(elem * (size_t)kMaxPanel * 16, kAlign);       // dinv
     t += align_up(sizeof(int) * (size_t)kMaxPanel, kAlign);     // stepflag
     t += align_up(2 * sizeof(int), kAlign);                     // claim
@@ -181,6 +181,9 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b, bool with_w)
     w.colsrc = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
     w.srcp = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.moved = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
+    w.colsrc_b = reinterpret_cast<int*>(take(sizeof(int) * (size_t)n));
+    w.srcp_b = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
+    w.moved_b = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.dinv = reinterpret_cast<T*>(take(sizeof(T) * (size_t)kMaxPanel * 16));
     w.stepflag = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.claim = reinterpret_cast<int*>(take(2 * sizeof(int)));
@@ -216,6 +219,15 @@ extern "C" const char* mc_status_string(mc_status status)
 extern "C" const char* mc_last_hip_error(void)
 {
     return hipGetErrorString(g_last_hip);
+}
+
+static bool g_lookahead_on = true;
+
+extern "C" int mc_lookahead_enable(int on)
+{
+    const int prev = g_lookahead_on ? 1 : 0;
+    g_lookahead_on = on != 0;
+    return prev;
 }
 
 extern "C" mc_status mc_profile_enable(int on)
@@ -629,13 +641,15 @@ extern "C" mc_status mc_logdet_factor(void* A, int64_t n, int64_t lda,
         w.W = static_cast<double*>(A);
         w.ldw = lda;
         w.perm = perm;
-        e = launch_blocked<double>(w.W, n, lda, b, update, w, out, st, true);
+        e = launch_blocked<double>(w.W, n, lda, b, update, w, out, st, true,
+                                   g_lookahead_on);
     } else {
         BlkWork<float> w = blocked_carve<float>(work, n, b, false);
         w.W = static_cast<float*>(A);
         w.ldw = lda;
         w.perm = perm;
-        e = launch_blocked<float>(w.W, n, lda, b, update, w, out, st, true);
+        e = launch_blocked<float>(w.W, n, lda, b, update, w, out, st, true,
+                                  g_lookahead_on);
     }
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
@@ -726,11 +740,11 @@ extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
             e = launch_blocked<double>(static_cast<const double*>(A), n, lda,
                                        b, update,
                                        blocked_carve<double>(work, n, b), out,
-                                       st);
+                                       st, false, g_lookahead_on);
         else
             e = launch_blocked<float>(static_cast<const float*>(A), n, lda, b,
                                       update, blocked_carve<float>(work, n, b),
-                                      out, st);
+                                      out, st, false, g_lookahead_on);
     }
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }

@@ -28,6 +28,7 @@
 //   blk_trsm_mfma  L21 = gather(A21) * U11^{-1} on the matrix cores
 //   gemm       A22 <- gather(A22) - L21 * U12    (mc_gemm.hip)
 #include <algorithm>
+#include <mutex>
 
 #include "mc_device.h"
 #include "mc_gemm.h"
@@ -51,9 +52,12 @@ blk_init(const T* __restrict__ A, int64_t lda, int64_t n, BlkWork<T> w)
         for (int64_t j = threadIdx.x; j < n; j += kBlkThreads) {
             w.perm[j] = (int)j;
             w.colsrc[j] = (int)j;
+            w.colsrc_b[j] = (int)j;
         }
-        for (int t = threadIdx.x; t < kMaxPanel; t += kBlkThreads)
+        for (int t = threadIdx.x; t < kMaxPanel; t += kBlkThreads) {
             w.moved[t] = -1;
+            w.moved_b[t] = -1;
+        }
         if (threadIdx.x == 0) {
             w.state->status = kStatusOk;
             w.state->bad_step = 0;
@@ -945,6 +949,8 @@ static void launch_panel_x(int64_t n, int64_t s0, int64_t pend,
         hipLaunchKernelGGL((blk_panel_x<T, NT, EPT, 4>), grid, block, 0, stream, n, s0, pend, nslots, w);
 }
 
+static bool panel_x_fits(int64_t width) { return width <= 768 * 11; }
+
 // Single-XCD panel for a row width; false when wider than it handles
 // (4 rows of up to 11 entries per thread keep every slot's rows in
 // registers).
@@ -957,7 +963,7 @@ static bool try_panel_x(int64_t n, int64_t s0, int64_t pend,
     else if (width <= 1024) launch_panel_x<T, 512, 2>(n, s0, pend, w, stream);
     else if (width <= 2048) launch_panel_x<T, 512, 4>(n, s0, pend, w, stream);
     else if (width <= 4096) launch_panel_x<T, 512, 8>(n, s0, pend, w, stream);
-    else if (width <= 768 * 11) launch_panel_x<T, 768, 11>(n, s0, pend, w, stream);
+    else if (panel_x_fits(width)) launch_panel_x<T, 768, 11>(n, s0, pend, w, stream);
     else return false;
     return true;
 }
@@ -1289,10 +1295,90 @@ static size_t trsm_mfma_lds_bytes(int nb)
     return sizeof(T) * (size_t)(kTrsmRows) * (size_t)(nblk * 16 + 1);
 }
 
+// ---- one-panel lookahead ----
+//
+// The next panel only needs its own rows brought up to date, so the
+// trailing update is split: the next panel's rows on the caller's stream,
+// the rest on a second stream, where it runs beside the next panel's
+// factorisation (whose chain occupies one XCD).  Fork and join are events;
+// the caller's stream waits for the join before the next triangular solve
+// and before returning.  One side stream and event pair per device, reused
+// under a lock held while a call enqueues its work.
+struct Lookahead {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool ready = false, failed = false;
+};
+
+constexpr int kMaxDevices = 64;
+static Lookahead g_lookahead[kMaxDevices];
+static std::mutex g_lookahead_mu;
+
+// The device's lookahead resources, created on first use; nullptr when
+// they cannot be created (the update then runs on one stream).
+static Lookahead* lookahead_get()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    Lookahead& la = g_lookahead[dev];
+    if (!la.ready && !la.failed) {
+        if (hipStreamCreateWithFlags(&la.side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&la.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&la.join, hipEventDisableTiming) != hipSuccess) {
+            la.failed = true;
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        la.ready = true;
+    }
+    return la.ready ? &la : nullptr;
+}
+
+// The panel-k view of the workspace: alternate column-map sets.
+template <typename T>
+static BlkWork<T> panel_view(const BlkWork<T>& w, int64_t k)
+{
+    BlkWork<T> v = w;
+    if (k & 1) {
+        v.colsrc = w.colsrc_b;
+        v.srcp = w.srcp_b;
+        v.moved = w.moved_b;
+    }
+    return v;
+}
+
+template <typename T>
+static hipError_t trailing(const BlkWork<T>& w, int update, int64_t s0, int nb,
+                           int64_t r0, int64_t m, int64_t n, hipStream_t st)
+{
+    const int64_t pend = s0 + nb;
+    GemmArgs<T> g;
+    g.C = w.W;
+    g.ldc = w.ldw;
+    g.r0 = r0;
+    g.c0 = pend;
+    g.M = m;
+    g.N = n - pend;
+    g.K = nb;
+    g.L = w.L + (r0 - pend) * w.ldl;
+    g.ldl = w.ldl;
+    g.U = w.W + s0 * w.ldw;
+    g.ldu = w.ldw;
+    g.colsrc = w.colsrc;
+    g.state = w.state;
+    const ProfMark pm = prof_begin(st);
+    const hipError_t e = launch_trailing_update(g, update, st);
+    if (e != hipSuccess) return e;
+    const double flops = 2.0 * (double)m * (double)g.N * nb;
+    const double bytes = (double)sizeof(T) * (2.0 * m * g.N + (double)m * nb + (double)nb * g.N);
+    prof_end(st, pm, 1, bytes, flops);
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                           int update, BlkWork<T> w, mc_result* out,
-                          hipStream_t stream, bool factor)
+                          hipStream_t stream, bool factor, bool lookahead)
 {
     static bool attr_set = false;
     if (!attr_set && trsm_mfma_lds_bytes<T>((int)kMaxPanel) > 64 * 1024) {
@@ -1305,7 +1391,10 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     }
     hipLaunchKernelGGL(blk_init<T>, dim3((unsigned)n), dim3(kBlkThreads), 0,
                        stream, A, lda, n, w);
-    for (int64_t s0 = 0; s0 < n; s0 += b) {
+    std::unique_lock<std::mutex> lock(g_lookahead_mu);
+    Lookahead* la = lookahead ? lookahead_get() : nullptr;
+    bool pending = false; // side-stream work the caller's stream must join
+    for (int64_t s0 = 0, k = 0; s0 < n; s0 += b, ++k) {
         const int nb = (int)std::min<int64_t>(b, n - s0);
         const int64_t pend = s0 + nb;
         launch_head<T>(n, s0, w, stream);
@@ -1334,41 +1423,49 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                                dim3(kBlkThreads), 0, stream, s0, nb, w);
         if (pend >= n) break;
         const int64_t rows = n - pend;
+        const BlkWork<T> wk = panel_view(w, k);
         hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
-                           s0, nb, w);
+                           s0, nb, wk);
+        if (pending) { // the previous panel's update of the rows below
+            const hipError_t e = hipStreamWaitEvent(stream, la->join, 0);
+            if (e != hipSuccess) return note_hip_error(e);
+            pending = false;
+        }
         hipLaunchKernelGGL(blk_trsm_mfma<T>,
                            dim3((unsigned)((rows + kTrsmRows - 1) / kTrsmRows)),
                            dim3(kBlkThreads), trsm_mfma_lds_bytes<T>(nb), stream,
-                           n, s0, nb, w);
-        GemmArgs<T> g;
-        g.C = w.W;
-        g.ldc = w.ldw;
-        g.r0 = pend;
-        g.c0 = pend;
-        g.M = rows;
-        g.N = rows;
-        g.K = nb;
-        g.L = w.L;
-        g.ldl = w.ldl;
-        g.U = w.W + s0 * w.ldw;
-        g.ldu = w.ldw;
-        g.colsrc = w.colsrc;
-        g.state = w.state;
-        const ProfMark pm = prof_begin(stream);
-        const hipError_t e = launch_trailing_update(g, update, stream);
+                           n, s0, nb, wk);
+        // the next panel's rows first, on the caller's stream
+        const int64_t next = std::min<int64_t>(b, rows);
+        hipError_t e = trailing(wk, update, s0, nb, pend, next, n, stream);
         if (e != hipSuccess) return e;
-        const double flops = 2.0 * (double)rows * (double)rows * nb;
-        const double bytes = (double)sizeof(T) *
-                             (2.0 * rows * rows + 2.0 * rows * nb);
-        prof_end(stream, pm, 1, bytes, flops);
+        hipStream_t rest = stream;
+        if (la && rows > next) {
+            if ((e = hipEventRecord(la->fork, stream)) != hipSuccess ||
+                (e = hipStreamWaitEvent(la->side, la->fork, 0)) != hipSuccess)
+                return note_hip_error(e);
+            rest = la->side;
+        }
+        if (rows > next) {
+            e = trailing(wk, update, s0, nb, pend + next, rows - next, n, rest);
+            if (e != hipSuccess) return e;
+        }
         if (factor) {
             hipLaunchKernelGGL(blk_store_l<T>, dim3(1024), dim3(kBlkThreads), 0,
-                               stream, n, s0, nb, w);
+                               rest, n, s0, nb, wk);
             if (s0 > 0)
                 hipLaunchKernelGGL(blk_swaps_above<T>,
                                    dim3((unsigned)((s0 + 3) / 4)),
-                                   dim3(kBlkThreads), 0, stream, s0, nb, w);
+                                   dim3(kBlkThreads), 0, rest, s0, nb, wk);
         }
+        if (rest != stream) {
+            if ((e = hipEventRecord(la->join, rest)) != hipSuccess) return note_hip_error(e);
+            pending = true;
+        }
+    }
+    if (pending) {
+        const hipError_t e = hipStreamWaitEvent(stream, la->join, 0);
+        if (e != hipSuccess) return note_hip_error(e);
     }
     // the last panel (no rows below): its exchanges still reach the rows
     // above it in factor mode
@@ -1376,10 +1473,11 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         const int64_t s0 = ((n - 1) / b) * b;
         const int nb = (int)(n - s0);
         if (s0 > 0) {
+            const BlkWork<T> wk = panel_view(w, s0 / b);
             hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
-                               s0, nb, w);
+                               s0, nb, wk);
             hipLaunchKernelGGL(blk_swaps_above<T>, dim3((unsigned)((s0 + 3) / 4)),
-                               dim3(kBlkThreads), 0, stream, s0, nb, w);
+                               dim3(kBlkThreads), 0, stream, s0, nb, wk);
         }
     }
     hipLaunchKernelGGL(blk_finalize, dim3(1), dim3(kBlkThreads), 0, stream, n,
@@ -1389,9 +1487,9 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
 
 template hipError_t launch_blocked<double>(const double*, int64_t, int64_t,
                                            int64_t, int, BlkWork<double>,
-                                           mc_result*, hipStream_t, bool);
+                                           mc_result*, hipStream_t, bool, bool);
 template hipError_t launch_blocked<float>(const float*, int64_t, int64_t,
                                           int64_t, int, BlkWork<float>,
-                                          mc_result*, hipStream_t, bool);
+                                          mc_result*, hipStream_t, bool, bool);
 
 } // namespace mc

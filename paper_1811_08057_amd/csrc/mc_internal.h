@@ -47,6 +47,12 @@ struct BlkWork {
     int* colsrc;   // source position of each trailing destination position
     int* srcp;     // source position of each panel column s0 + t
     int* moved;    // trailing positions remapped by the previous panel
+    // second set of the three above: consecutive panels alternate, so a
+    // panel's trailing update can still read its set while the next panel
+    // fills the other
+    int* colsrc_b;
+    int* srcp_b;
+    int* moved_b;
     T* dinv;       // inverses of the 16 x 16 diagonal blocks of U11
     int* stepflag; // per panel step: 1 once its pivot row is published
     int* claim;    // single-XCD panel kernel: [0] row-claim counter, [1] elected XCD
@@ -62,7 +68,7 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b,
 template <typename T>
 hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                           int update, BlkWork<T> w, mc_result* out,
-                          hipStream_t stream, bool factor = false);
+                          hipStream_t stream, bool factor, bool lookahead);
 
 size_t plain_workspace_bytes(int64_t n);
 PlainWork plain_carve(void* work, int64_t n);

@@ -162,3 +162,52 @@ def test_blocked_f32_normal(update):
         got = run(a, 32, update=update, dtype=torch.float32)
         assert got.sign == ref.sign and got.info == 0
         assert rel(got, ref) <= TOL_MIXED, (n, got, ref, rel(got, ref))
+
+
+@pytest.mark.parametrize("n,b", [(300, 32), (1000, 64), (1300, 128)])
+def test_lookahead_on_and_off_agree(n, b):
+    """The trailing update split across two streams (the default) and the
+    single-stream schedule give the same answer, both within the FP64 bar
+    of the oracle; so does the factor call."""
+    a_np = synth.normal(n, 70 + n)
+    ref = O.slogdet(a_np)
+    prev = mc.lookahead_enable(True)
+    try:
+        on = run(a_np, b)
+        lu_on, perm_on, _ = mc.factor(torch.from_numpy(a_np).to(DEV), b=b)
+        mc.lookahead_enable(False)
+        off = run(a_np, b)
+        lu_off, perm_off, _ = mc.factor(torch.from_numpy(a_np).to(DEV), b=b)
+    finally:
+        mc.lookahead_enable(prev)
+    assert_parity(on, ref)
+    assert_parity(off, ref)
+    assert abs(on.logabsdet - off.logabsdet) <= 1e-12 * max(1.0, abs(ref.logabsdet))
+    assert torch.equal(perm_on, perm_off)
+    err = (lu_on - lu_off).abs().max().item()
+    assert err <= 1e-10 * max(1.0, lu_off.abs().max().item()), err
+
+
+def test_blocked_graph_replays_with_lookahead():
+    """mc_logdet on the blocked path (side-stream trailing updates joined by
+    events) captured into a graph and replayed, with eager work and
+    synchronisations between replays; every replay gives the eager result."""
+    n, b = 700, 64
+    a_np = synth.normal(n, 5)
+    a = torch.from_numpy(a_np).to(DEV)
+    work = mc.new_workspace(n, DEV, torch.float64, "native", b)
+    res = mc.new_result(DEV)
+    mc.logdet_async(a, res, work, b=b)
+    eager = mc.read_result(res)[0]
+    assert_parity(eager, O.slogdet(a_np))
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        mc.logdet_async(a, res, work, b=b, stream=stream)
+    for rep in range(4):
+        res.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert mc.read_result(res)[0] == eager, f"replay {rep}"
