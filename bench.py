@@ -1,21 +1,26 @@
 """Throughput benchmark of the condensation log-determinant on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path plain|blocked]
-                    [--workload NAME] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path blocked|plain]
+                    [--b B] [--workload NAME] [--no-plain] [--no-cpu]
 
 A step is one whole log-determinant of the workload matrix (every stage of
-the path: pivot searches, row factoring, updates, log/sign accumulation).
-Inputs are resident in HBM before the timed region starts.  Prints ONE JSON
-line with the metric, a roofline object for the dominant kernel (HIP events
-recorded on the launch stream by the library) and the CPU oracle timed on a
-bounded sample of the same workload.
+the path: pivot searches, row factoring, updates, log/sign accumulation),
+with the matrix resident in HBM before the timed region starts.  The
+headline is the panel-blocked path (MFMA trailing updates) on the dense
+N = 8000 FP64 N(0,1) matrix; the plain unblocked FP64 GPU path is timed on
+the same matrix beside it.  Prints ONE JSON line with the metric, a
+roofline object for the kernel that dominates the timed steps (HIP events
+the library records on the stream each kernel runs on), and the CPU oracle
+timed on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,9 +31,22 @@ METRIC = "log-dets/s and GFLOP/s (2N³/3) vs plain FP64 GPU at stated rel. error
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
-# Paper, Table 3: best matrix-condensation time for N = 8000 (FP64, 128
-# Haswell cores over MPI) = 7.17 s.  Context, not a target.
+# Matrix condensation, Table 3: best time for N = 8000 (FP64, 128 Haswell
+# cores over MPI) = 7.17 s.  Another machine's number: context, not a target.
 PAPER_BEST_N8000_S = 7.17
+
+# Source file of each timed kernel kind (a stored HBM-traffic measurement is
+# used only while the source it was taken on is unchanged).
+KERNEL_SOURCE = {
+    "panel": "paper_1811_08057_amd/csrc/mc_blocked.hip",
+    "update": "paper_1811_08057_amd/csrc/mc_gemm.hip",
+    "plain_step": "paper_1811_08057_amd/csrc/mc_plain.hip",
+}
+KERNEL_NAME = {
+    "panel": "blk_panel_x (panel chain, single XCD)",
+    "update": "gemm_scalar (trailing update, FP64 MFMA)",
+    "plain_step": "plain_step (unblocked condensation step)",
+}
 
 
 def parse():
@@ -36,12 +54,49 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
-    p.add_argument("--path", default="plain", choices=["plain", "blocked"])
-    p.add_argument("--b", type=int, default=128)
+    p.add_argument("--path", default="blocked", choices=["plain", "blocked"])
+    p.add_argument("--b", type=int, default=-1,
+                   help="panel width of the blocked path (-1: library default)")
     p.add_argument("--workload", default="normal_n8000")
+    p.add_argument("--no-plain", action="store_true",
+                   help="skip timing the plain FP64 GPU path beside it")
+    p.add_argument("--plain-steps", type=int, default=2)
+    p.add_argument("--lookahead", default="off", choices=["on", "off"],
+                   help="blocked path: split trailing updates over two "
+                        "streams (on) or keep one stream (off)")
+    p.add_argument("--profile-steps", type=int, default=3,
+                   help="steps of the separate kernel-timing pass")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                   help="only run a device-to-device copy of BYTES bytes "
+                        "three times (the reference kernel for scaling the "
+                        "HBM counters FETCH_SIZE / WRITE_SIZE)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     return p.parse_args()
+
+
+def sha256_of(rel: str) -> str:
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic(kind: str, workload: str, b: int):
+    """HBM bytes per launch of the kernel kind, from the committed rocprofv3
+    counter summary for this workload, if its recorded source hash still
+    matches the kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    fields = dict(re.findall(r"^- (\w+): (\S+)\s*$", text, re.M))
+    try:
+        if fields.get("source_sha256") != sha256_of(KERNEL_SOURCE[kind]):
+            return None
+        if int(fields.get("b", -2)) != b:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(a, target_s: float):
@@ -76,6 +131,58 @@ def cpu_baseline(a, target_s: float):
             "gflops": (2.0 * n ** 3 / 3.0) / full / 1e9}
 
 
+def timed(mc, torch, a, b, steps, warmup, stream, profile=False):
+    """ms per log-det over `steps` calls after `warmup`; returns
+    (ms_per_step, last result, library kernel profiles by kind or None).
+    The library's kernel timing puts an event pair around every timed
+    launch, which perturbs the schedule, so the headline pass runs without
+    it and the kernel averages come from a separate pass."""
+    n = a.shape[0]
+    dev = a.device
+    work = mc.new_workspace(n, dev, a.dtype, "native", b)
+    res = mc.new_result(dev, 1)
+    for _ in range(warmup):
+        mc.logdet_async(a, res, work, b=b)
+    torch.cuda.synchronize()
+    if profile:
+        mc.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        mc.logdet_async(a, res, work, b=b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    prof = None
+    if profile:
+        prof = {k: mc.profile_read(k) for k in ("update", "panel")}
+        mc.profile_enable(False)
+    return e0.elapsed_time(e1) / steps, mc.read_result(res)[0], prof
+
+
+def roofline_of(kind, p, workload, b):
+    """Roofline entry for one timed kernel kind (p: library profile)."""
+    if p.launches == 0 or p.elapsed_ms <= 0:
+        return None
+    avg_us = p.elapsed_ms * 1e3 / p.launches
+    if kind == "update":
+        ach = p.alg_flops / (p.elapsed_ms * 1e-3) / 1e12
+        r = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFS,
+             "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFS}
+    else:
+        ach = p.alg_bytes / (p.elapsed_ms * 1e-3) / 1e9
+        r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    r["traffic"] = stored_traffic(kind, workload, b)
+    r.update({"kernel": KERNEL_NAME[kind], "launches": p.launches,
+              "avg_launch_us": avg_us,
+              "alg_bytes_per_launch": p.alg_bytes / p.launches,
+              "alg_flops_per_launch": p.alg_flops / p.launches,
+              "share_of_step": None})
+    return r
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -83,7 +190,6 @@ def main():
                           f"--gpus {args.gpus} is not supported (use 1)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1811_08057_amd as mc
@@ -93,69 +199,64 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy // 8 * 8
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb,
+                          "launches": 3}), flush=True)
+        return
     spec = synth.CONFIGS[args.workload]
     n = spec["n"]
-    b = 0 if args.path == "plain" else args.b
-    steps = args.steps if args.steps is not None else (3 if b == 0 else 20)
+    plain = args.path == "plain"
+    b = 0 if plain else args.b
+    if b < 0:
+        b = mc.default_panel(n)
+    steps = args.steps if args.steps is not None else (3 if plain else 20)
     warmup = args.warmup if args.warmup is not None else 1
+    stream = torch.cuda.current_stream(dev)
 
     print(f"# generating {args.workload}", file=sys.stderr, flush=True)
     a_np = synth.make(args.workload)
     a = torch.from_numpy(a_np).to(dev)
-    work = mc.new_workspace(n, dev, torch.float64, "native", b)
-    res = mc.new_result(dev, 1)
-    stream = torch.cuda.current_stream(dev)
 
-    print(f"# warmup {warmup} x {args.path}", file=sys.stderr, flush=True)
-    for _ in range(warmup):
-        mc.logdet_async(a, res, work, b=b)
-    torch.cuda.synchronize()
-
-    print(f"# timing {steps} steps", file=sys.stderr, flush=True)
-    mc.profile_enable(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(steps):
-        mc.logdet_async(a, res, work, b=b)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    prof = mc.profile_read()
-    mc.profile_enable(False)
-    ms = e0.elapsed_time(e1)
-    got = mc.read_result(res)[0]
-    ms_per_step = ms / steps
+    if not plain:
+        mc.lookahead_enable(args.lookahead == "on")
+    print(f"# {args.path} b={b}: warmup {warmup}, timing {steps}",
+          file=sys.stderr, flush=True)
+    ms_per_step, got, _ = timed(mc, torch, a, b, steps, warmup, stream)
+    print(f"# kernel timing pass: {args.profile_steps} steps",
+          file=sys.stderr, flush=True)
+    prof_ms, _, prof = timed(mc, torch, a, b, args.profile_steps, 0, stream,
+                             profile=True)
     value = 1000.0 / ms_per_step
     gflops = (2.0 * n ** 3 / 3.0) / (ms_per_step * 1e-3) / 1e9
 
-    # accuracy against the stored oracle value for this workload, if any
-    rel_err, sign_ok = None, None
+    # accuracy against the stored oracle value for this workload
+    exp, rel_err, sign_ok = None, None, None
     exp_path = os.path.join(ROOT, "tests", "golden",
                             f"expected_{args.workload}.json")
     if os.path.exists(exp_path):
         with open(exp_path) as f:
-            e = json.load(f)["f64"]
-        rel_err = abs(got.logabsdet - e["logabsdet"]) / max(
-            abs(e["logabsdet"]), 1.0)
-        sign_ok = got.sign == e["sign"]
+            exp = json.load(f)["f64"]
+        rel_err = abs(got.logabsdet - exp["logabsdet"]) / max(
+            abs(exp["logabsdet"]), 1.0)
+        sign_ok = got.sign == exp["sign"]
 
-    if b == 0:
-        achieved = prof.alg_bytes / (prof.elapsed_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "plain_step", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "launches": prof.launches,
-                "avg_launch_us": prof.elapsed_ms * 1e3 / max(prof.launches, 1),
-                "note": ("algorithmic bytes = 16 (m-1)^2 per step; events "
-                         "bracket the run of per-step launches")}
-    else:
-        achieved = prof.alg_flops / (prof.elapsed_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "trailing_update",
-                "achieved": achieved, "peak": FP64_PEAK_TFS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS,
-                "traffic": None, "launches": prof.launches,
-                "avg_launch_us": prof.elapsed_ms * 1e3 / max(prof.launches, 1)}
+    # roofline of the dominant kernel (largest timed share of the step)
+    entries = {}
+    for k in (["plain_step"] if plain else ["panel", "update"]):
+        p = prof["update" if k == "plain_step" else k]
+        r = roofline_of(k, p, args.workload, b)
+        if r is not None:
+            r["share_of_step"] = p.elapsed_ms / args.profile_steps / prof_ms
+            r["timing_pass_ms_per_step"] = prof_ms
+            entries[k] = r
+    dominant = max(entries, key=lambda k: entries[k]["share_of_step"])
+    roof = dict(entries[dominant])
 
     out = {
         "metric": METRIC, "value": value, "unit": "log-dets/s",
@@ -167,11 +268,30 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n,
                    "dist": spec["kind"], "seed": spec.get("seed"),
-                   "path": args.path, "b": b},
+                   "path": args.path, "b": b,
+                   "lookahead": None if plain else args.lookahead},
         "gflops": gflops,
         "rel_err_vs_oracle": rel_err, "sign_matches_oracle": sign_ok,
         "roofline": roof,
+        "kernels": entries,
     }
+
+    if not plain and not args.no_plain:
+        print(f"# plain FP64 GPU path: {args.plain_steps} steps",
+              file=sys.stderr, flush=True)
+        pms, pgot, pprof = timed(mc, torch, a, 0, args.plain_steps, 1, stream,
+                                 profile=True)
+        p = pprof["update"]
+        pach = p.alg_bytes / (p.elapsed_ms * 1e-3) / 1e9
+        out["plain_fp64_gpu"] = {
+            "ms_per_step": pms, "value": 1000.0 / pms,
+            "gflops": (2.0 * n ** 3 / 3.0) / (pms * 1e-3) / 1e9,
+            "rel_err_vs_oracle": (abs(pgot.logabsdet - exp["logabsdet"]) /
+                                  max(abs(exp["logabsdet"]), 1.0)
+                                  if exp else None),
+            "hbm_achieved_gbs": pach, "hbm_frac": pach / HBM_PEAK_GBS}
+        out["speedup_vs_plain_fp64_gpu"] = pms / ms_per_step
+
     if not args.no_cpu:
         print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a_np, args.cpu_seconds)

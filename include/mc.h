@@ -92,6 +92,13 @@ const char* mc_last_hip_error(void);
 size_t mc_logdet_workspace(int64_t n, int dtype, int update, int64_t b);
 
 /*
+ * The panel width the blocked path uses for b < 0 (the library default) on
+ * an n x n matrix of the given mc_dtype: 32 up to n = 256, 64 up to 1024,
+ * 128 above.  n < 0: 0.
+ */
+int64_t mc_default_panel(int64_t n, int dtype);
+
+/*
  * log|det A| and sign of one n x n matrix.
  *
  * A       device, row-major n x n, row stride lda (elements); read only.
@@ -212,7 +219,7 @@ mc_status mc_autotune_batched(int dtype, int update, int64_t n_max_tune,
                               void* work, size_t work_bytes, void* stream);
 
 /*
- * Blocked path scheduling.  With lookahead on (the default), each panel's
+ * Blocked path scheduling.  With lookahead on (off by default), each panel's
  * trailing update is split: the rows of the next panel are updated on the
  * caller's stream, the remaining rows on a second stream the library owns
  * (one per device, default priority), where that update runs beside the
@@ -222,27 +229,41 @@ mc_status mc_autotune_batched(int dtype, int update, int64_t n_max_tune,
  * be captured into a graph).  Off: every kernel runs on the caller's
  * stream.  Returns the previous setting (1 on, 0 off).  Process-wide;
  * calls that enqueue blocked work are serialised on a lock while they do.
+ * Off is the default because the side stream's update tiles also land on
+ * the XCD that runs the panel chain and slow that chain more than the
+ * overlap gains (measured on MI355X at N = 8000: 87 ms on, 60 ms off).
  */
 int mc_lookahead_enable(int on);
 
 /*
- * Optional timing of the kernel that dominates a call: the condensation
- * update of the plain path (timed as the whole run of per-step launches).
- * While enabled, each call records a pair of HIP events on its stream
- * around those launches and adds the launches' algorithmic traffic: for
- * the plain path 16 bytes per updated FP64 entry (one read, one write of
- * the live block, Figure 6 step 4.11) and 2 flops per entry.
+ * Optional timing of the kernels that dominate a call, in two kinds:
  *
- * mc_profile_enable(1) resets the counters and starts recording;
- * mc_profile_enable(0) stops.  Host-side, not thread-safe; at most 4096
- * event pairs are kept (later launches are counted but not timed).
- * mc_profile_read synchronises on the recorded events and returns the
- * summed elapsed time (ms), the number of kernel launches covered, and the
- * algorithmic bytes and flops of those launches.  Pointers are host
- * pointers; any may be NULL.
+ * MC_PROF_UPDATE  the condensation update.  Plain path: the whole run of
+ *                 per-step launches, 16 algorithmic bytes (one read, one
+ *                 write of the live block, Figure 6 step 4.11) and 2 flops
+ *                 per updated FP64 entry.  Blocked path: each trailing
+ *                 update launch (Section 2.5's block form), 2 m N b flops
+ *                 and sizeof(T) (2 m N + m b + b N) bytes for an m x N
+ *                 update of panel width b.
+ * MC_PROF_PANEL   the blocked path's panel-chain kernel (the b condensation
+ *                 steps of one panel, one launch per panel): the panel's
+ *                 rows read once and written once, 2 b w sizeof(T) bytes for
+ *                 w active columns, and about 2 b^2 w / 2 flops.
+ *
+ * While enabled, each such launch is bracketed by a pair of HIP events on
+ * the stream it runs on.  mc_profile_enable(1) resets the counters and
+ * starts recording; mc_profile_enable(0) stops.  Host-side, not
+ * thread-safe; at most 4096 event pairs are kept (later launches are
+ * counted but not timed).  mc_profile_read synchronises on the recorded
+ * events of one kind and returns their summed elapsed time (ms), the number
+ * of kernel launches covered, and the algorithmic bytes and flops of those
+ * launches.  Pointers are host pointers; any may be NULL.  kind other than
+ * the two: -1.
  */
+#define MC_PROF_UPDATE 0
+#define MC_PROF_PANEL 1
 mc_status mc_profile_enable(int on);
-mc_status mc_profile_read(double* elapsed_ms, int64_t* launches,
+mc_status mc_profile_read(int kind, double* elapsed_ms, int64_t* launches,
                           double* alg_bytes, double* alg_flops);
 
 #ifdef __cplusplus

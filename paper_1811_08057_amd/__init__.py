@@ -36,7 +36,7 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_tune_set", "mc_autotune_workspace", "mc_autotune_batched",
            "mc_last_hip_error", "mc_logdet_factor_workspace",
            "mc_logdet_factor", "mc_logdet_backward_workspace",
-           "mc_logdet_backward", "mc_lookahead_enable")
+           "mc_logdet_backward", "mc_lookahead_enable", "mc_default_panel")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -75,11 +75,13 @@ def lib() -> ctypes.CDLL:
                             vp, sz, vp]
     L.mc_logdet.restype = ctypes.c_int
     dp = ctypes.POINTER(ctypes.c_double)
+    L.mc_default_panel.argtypes = [ctypes.c_int64, ctypes.c_int]
+    L.mc_default_panel.restype = ctypes.c_int64
     L.mc_lookahead_enable.argtypes = [ctypes.c_int]
     L.mc_lookahead_enable.restype = ctypes.c_int
     L.mc_profile_enable.argtypes = [ctypes.c_int]
     L.mc_profile_enable.restype = ctypes.c_int
-    L.mc_profile_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), dp, dp]
+    L.mc_profile_read.argtypes = [ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64), dp, dp]
     L.mc_profile_read.restype = ctypes.c_int
     ci = ctypes.c_int
     L.mc_logdet_batched_workspace.argtypes = [i64, i64, ci, ci, i64]
@@ -205,9 +207,14 @@ class Profile(NamedTuple):
     alg_flops: float
 
 
+def default_panel(n: int, dtype=torch.float64) -> int:
+    """Panel width the blocked path takes for b < 0 on an n x n matrix."""
+    return int(lib().mc_default_panel(n, _dtype_of(dtype)))
+
+
 def lookahead_enable(on: bool = True) -> bool:
-    """Split each blocked trailing update across two streams (the default)
-    or keep every kernel on the caller's stream; returns the previous
+    """Split each blocked trailing update across two streams, or keep every
+    kernel on the caller's stream (the default); returns the previous
     setting."""
     return bool(lib().mc_lookahead_enable(1 if on else 0))
 
@@ -217,10 +224,14 @@ def profile_enable(on: bool = True) -> None:
     _check(lib().mc_profile_enable(1 if on else 0), "mc_profile_enable")
 
 
-def profile_read() -> Profile:
+def profile_read(kind: str = "update") -> Profile:
+    """Summed event timing and algorithmic work of one kind of kernel since
+    profile_enable: "update" (trailing update / plain step loop) or
+    "panel" (the blocked path's panel-chain kernel)."""
+    k = {"update": 0, "panel": 1}[kind]
     ms, la = ctypes.c_double(), ctypes.c_int64()
     by, fl = ctypes.c_double(), ctypes.c_double()
-    _check(lib().mc_profile_read(ctypes.byref(ms), ctypes.byref(la),
+    _check(lib().mc_profile_read(k, ctypes.byref(ms), ctypes.byref(la),
                                  ctypes.byref(by), ctypes.byref(fl)),
            "mc_profile_read")
     return Profile(ms.value, la.value, by.value, fl.value)

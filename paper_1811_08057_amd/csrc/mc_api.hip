@@ -52,18 +52,20 @@ constexpr int kMaxProfPairs = 4096;
 struct Profiler {
     bool on = false;
     std::vector<hipEvent_t> begin, end; // created lazily, reused
+    std::vector<int> kind;
     int used = 0;
-    int64_t launches = 0;
-    double bytes = 0.0, flops = 0.0;
+    int64_t launches[2] = {0, 0};
+    double bytes[2] = {0.0, 0.0}, flops[2] = {0.0, 0.0};
 };
 
 Profiler g_prof;
 
 } // namespace
 
-ProfMark prof_begin(hipStream_t stream)
+ProfMark prof_begin(hipStream_t stream, int kind)
 {
     ProfMark m;
+    m.kind = kind == MC_PROF_PANEL ? MC_PROF_PANEL : MC_PROF_UPDATE;
     if (!g_prof.on || g_prof.used >= kMaxProfPairs) return m;
     const int i = g_prof.used;
     if (i >= (int)g_prof.begin.size()) {
@@ -75,8 +77,10 @@ ProfMark prof_begin(hipStream_t stream)
         }
         g_prof.begin.push_back(a);
         g_prof.end.push_back(b);
+        g_prof.kind.push_back(0);
     }
     if (hipEventRecord(g_prof.begin[i], stream) != hipSuccess) return m;
+    g_prof.kind[i] = m.kind;
     g_prof.used = i + 1;
     m.slot = i;
     return m;
@@ -86,9 +90,9 @@ void prof_end(hipStream_t stream, ProfMark m, int64_t launches,
               double alg_bytes, double alg_flops)
 {
     if (!g_prof.on) return;
-    g_prof.launches += launches;
-    g_prof.bytes += alg_bytes;
-    g_prof.flops += alg_flops;
+    g_prof.launches[m.kind] += launches;
+    g_prof.bytes[m.kind] += alg_bytes;
+    g_prof.flops[m.kind] += alg_flops;
     if (m.slot >= 0) (void)hipEventRecord(g_prof.end[m.slot], stream);
 }
 
@@ -221,7 +225,7 @@ extern "C" const char* mc_last_hip_error(void)
     return hipGetErrorString(g_last_hip);
 }
 
-static bool g_lookahead_on = true;
+static bool g_lookahead_on = false;
 
 extern "C" int mc_lookahead_enable(int on)
 {
@@ -235,17 +239,22 @@ extern "C" mc_status mc_profile_enable(int on)
     g_prof.on = on != 0;
     if (g_prof.on) {
         g_prof.used = 0;
-        g_prof.launches = 0;
-        g_prof.bytes = g_prof.flops = 0.0;
+        for (int k = 0; k < 2; ++k) {
+            g_prof.launches[k] = 0;
+            g_prof.bytes[k] = g_prof.flops[k] = 0.0;
+        }
     }
     return MC_OK;
 }
 
-extern "C" mc_status mc_profile_read(double* elapsed_ms, int64_t* launches,
-                                     double* alg_bytes, double* alg_flops)
+extern "C" mc_status mc_profile_read(int kind, double* elapsed_ms,
+                                     int64_t* launches, double* alg_bytes,
+                                     double* alg_flops)
 {
+    if (kind != MC_PROF_UPDATE && kind != MC_PROF_PANEL) return -1;
     double total = 0.0;
     for (int i = 0; i < g_prof.used; ++i) {
+        if (g_prof.kind[i] != kind) continue;
         if (hipEventSynchronize(g_prof.end[i]) != hipSuccess) return MC_ERR_HIP;
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, g_prof.begin[i], g_prof.end[i]) !=
@@ -254,9 +263,9 @@ extern "C" mc_status mc_profile_read(double* elapsed_ms, int64_t* launches,
         total += ms;
     }
     if (elapsed_ms) *elapsed_ms = total;
-    if (launches) *launches = g_prof.launches;
-    if (alg_bytes) *alg_bytes = g_prof.bytes;
-    if (alg_flops) *alg_flops = g_prof.flops;
+    if (launches) *launches = g_prof.launches[kind];
+    if (alg_bytes) *alg_bytes = g_prof.bytes[kind];
+    if (alg_flops) *alg_flops = g_prof.flops[kind];
     return MC_OK;
 }
 
@@ -272,6 +281,11 @@ static int64_t default_panel(int64_t n, int dtype)
     if (n <= 256) return 32;
     if (n <= 1024) return 64;
     return 128;
+}
+
+extern "C" int64_t mc_default_panel(int64_t n, int dtype)
+{
+    return n < 0 ? 0 : default_panel(n, dtype);
 }
 
 static bool blocked_supported(int dtype, int update, int64_t b)

@@ -1400,6 +1400,7 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         launch_head<T>(n, s0, w, stream);
         const int ept = step_ept(n - s0);
         const bool persistent = ept > 0 && nb > 1;
+        const ProfMark pm = prof_begin(stream, MC_PROF_PANEL);
         const bool single_xcd = persistent && try_panel_x<T>(n, s0, pend, w, stream);
         if (persistent && !single_xcd) {
             switch (ept) { // wider than the single-XCD panel: across XCDs
@@ -1414,6 +1415,11 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         } else if (!persistent) {
             for (int64_t s = s0; s < pend; ++s)
                 launch_step<T>(n, s, s0, pend, w, stream);
+        }
+        { // the panel's rows read and written once; b^2 w flops
+            const double width = (double)(n - s0);
+            prof_end(stream, pm, persistent ? 1 : nb,
+                     2.0 * sizeof(T) * nb * width, (double)nb * nb * width);
         }
         if (single_xcd) // unfactored rows; the later steps' exchanges
             hipLaunchKernelGGL(blk_fixup_x<T>, dim3((unsigned)nb),

@@ -78,11 +78,15 @@ hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
 hipError_t launch_write_result(mc_result* out, double logabsdet, double sign,
                                int64_t info, hipStream_t stream);
 
-// Optional event timing of the dominant kernel (mc_profile_enable).
+// Optional event timing (mc_profile_enable) of two kinds of kernel:
+// MC_PROF_UPDATE (the condensation update: the trailing update of the
+// blocked path, the per-step loop of the plain path) and MC_PROF_PANEL (the
+// panel-chain kernel of the blocked path).
 struct ProfMark {
     int slot = -1;
+    int kind = 0;
 };
-ProfMark prof_begin(hipStream_t stream);
+ProfMark prof_begin(hipStream_t stream, int kind = MC_PROF_UPDATE);
 void prof_end(hipStream_t stream, ProfMark m, int64_t launches,
               double alg_bytes, double alg_flops);
 

@@ -73,11 +73,11 @@ def wishart(n: int, seed: int, m_factor: int = 2, ridge: float = RIDGE,
 
 
 def wishart_batch(count: int, lo: int, hi: int, seed: int,
-                  m_factor: int = 2, ridge: float = RIDGE):
+                  m_factor: int = 2, ridge: float = RIDGE, gram=None):
     """Sizes ~ U{lo..hi} then one Wishart matrix per size, one stream."""
     g = rng(seed)
     sizes = g.integers(lo, hi + 1, count)
-    mats = [wishart_from(g, int(n), m_factor, ridge) for n in sizes]
+    mats = [wishart_from(g, int(n), m_factor, ridge, gram) for n in sizes]
     return [int(n) for n in sizes], mats
 
 
@@ -128,5 +128,6 @@ def make(name: str, **kw):
     if kind == "wishart":
         return wishart(c["n"], c["seed"], gram=c.get("gram"))
     if kind == "wishart_batch":
-        return wishart_batch(c["count"], c["lo"], c["hi"], c["seed"])
+        return wishart_batch(c["count"], c["lo"], c["hi"], c["seed"],
+                             gram=c.get("gram"))
     raise KeyError(kind)

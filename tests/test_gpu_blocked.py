@@ -166,8 +166,8 @@ def test_blocked_f32_normal(update):
 
 @pytest.mark.parametrize("n,b", [(300, 32), (1000, 64), (1300, 128)])
 def test_lookahead_on_and_off_agree(n, b):
-    """The trailing update split across two streams (the default) and the
-    single-stream schedule give the same answer, both within the FP64 bar
+    """The trailing update split across two streams and the single-stream
+    schedule (the default) give the same answer, both within the FP64 bar
     of the oracle; so does the factor call."""
     a_np = synth.normal(n, 70 + n)
     ref = O.slogdet(a_np)
@@ -188,10 +188,20 @@ def test_lookahead_on_and_off_agree(n, b):
     assert err <= 1e-10 * max(1.0, lu_off.abs().max().item()), err
 
 
-def test_blocked_graph_replays_with_lookahead():
-    """mc_logdet on the blocked path (side-stream trailing updates joined by
-    events) captured into a graph and replayed, with eager work and
-    synchronisations between replays; every replay gives the eager result."""
+@pytest.mark.parametrize("lookahead", [False, True])
+def test_blocked_graph_replays(lookahead):
+    """mc_logdet on the blocked path (with lookahead: side-stream trailing
+    updates joined by events) captured into a graph and replayed, with eager
+    work and synchronisations between replays; every replay gives the eager
+    result."""
+    prev = mc.lookahead_enable(lookahead)
+    try:
+        _graph_replays()
+    finally:
+        mc.lookahead_enable(prev)
+
+
+def _graph_replays():
     n, b = 700, 64
     a_np = synth.normal(n, 5)
     a = torch.from_numpy(a_np).to(DEV)
@@ -211,3 +221,43 @@ def test_blocked_graph_replays_with_lookahead():
         graph.replay()
         torch.cuda.synchronize()
         assert mc.read_result(res)[0] == eager, f"replay {rep}"
+
+
+@pytest.fixture(scope="module")
+def wishart_n16384():
+    """The N = 16384 Wishart workload (seed 3): the same draws as the
+    stored oracle values, with X^T X formed on the GPU in FP64 (it differs
+    from the host product by rounding, which moves log|det| by ~1e-12
+    relative)."""
+    def gram(x):
+        xd = torch.from_numpy(x).to(DEV)
+        g = torch.matmul(xd.t().contiguous(), xd).cpu().numpy()
+        del xd
+        torch.cuda.empty_cache()
+        return g
+
+    print("[blocked] generating wishart_n16384", flush=True)
+    return synth.make("wishart_n16384", gram=gram)
+
+
+@pytest.mark.parametrize("precision,update", [("f64", "native"),
+                                              ("f32", "f32"),
+                                              ("f32", "bf16x3")])
+def test_wishart_n16384_expected(wishart_n16384, precision, update):
+    """The SPD covariance workload N = 16384 against the stored FP64 oracle
+    values (tests/golden/make_expected.py): FP64 storage within 1e-9; FP32
+    storage (FP32 or split-BF16x3 trailing updates) within 1e-5 of the
+    oracle on the FP32-rounded input.  The error against the FP64 oracle
+    on the FP64 input is printed too."""
+    with open(os.path.join(GOLDEN, "expected_wishart_n16384.json")) as f:
+        exp = json.load(f)
+    a = wishart_n16384
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    got = run(a, -1, update=update, dtype=dtype)
+    ref = exp[precision]
+    ref = O.SlogdetResult(ref["sign"], ref["logabsdet"], ref["info"])
+    assert_parity(got, ref, TOL64 if precision == "f64" else TOL_MIXED)
+    e64 = exp["f64"]["logabsdet"]
+    print(f"[blocked] wishart_n16384 {precision}/{update}: rel err "
+          f"{rel(got, ref):.3e} (vs FP64 oracle on FP64 input "
+          f"{abs(got.logabsdet - e64) / abs(e64):.3e})")
