@@ -31,6 +31,7 @@ METRIC = "log-dets/s and GFLOP/s (2N³/3) vs plain FP64 GPU at stated rel. error
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
+BF16_PEAK_TFS = 2500.0  # dense MFMA
 # Matrix condensation, Table 3: best time for N = 8000 (FP64, 128 Haswell
 # cores over MPI) = 7.17 s.  Another machine's number: context, not a target.
 PAPER_BEST_N8000_S = 7.17
@@ -43,8 +44,11 @@ KERNEL_SOURCE = {
     "plain_step": "paper_1811_08057_amd/csrc/mc_plain.hip",
 }
 KERNEL_NAME = {
-    "panel": "blk_panel_x (panel chain, single XCD)",
+    "panel": ("panel chain: blk_panel_x (one XCD; blk_panel across XCDs for "
+              "panels wider than 8448 columns)"),
     "update": "gemm_scalar (trailing update, FP64 MFMA)",
+    "update_f32": "gemm_scalar (trailing update, FP32 MFMA)",
+    "update_bf16x3": "gemm_bf16x3 (trailing update, split-BF16x3 MFMA)",
     "plain_step": "plain_step (unblocked condensation step)",
 }
 
@@ -58,6 +62,9 @@ def parse():
     p.add_argument("--b", type=int, default=-1,
                    help="panel width of the blocked path (-1: library default)")
     p.add_argument("--workload", default="normal_n8000")
+    p.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3"],
+                   help="f64: FP64 storage and MFMA updates; f32 / bf16x3: "
+                        "FP32 storage with FP32 or split-BF16x3 MFMA updates")
     p.add_argument("--no-plain", action="store_true",
                    help="skip timing the plain FP64 GPU path beside it")
     p.add_argument("--plain-steps", type=int, default=2)
@@ -131,7 +138,8 @@ def cpu_baseline(a, target_s: float):
             "gflops": (2.0 * n ** 3 / 3.0) / full / 1e9}
 
 
-def timed(mc, torch, a, b, steps, warmup, stream, profile=False):
+def timed(mc, torch, a, b, steps, warmup, stream, profile=False,
+          update="native"):
     """ms per log-det over `steps` calls after `warmup`; returns
     (ms_per_step, last result, library kernel profiles by kind or None).
     The library's kernel timing puts an event pair around every timed
@@ -139,10 +147,10 @@ def timed(mc, torch, a, b, steps, warmup, stream, profile=False):
     it and the kernel averages come from a separate pass."""
     n = a.shape[0]
     dev = a.device
-    work = mc.new_workspace(n, dev, a.dtype, "native", b)
+    work = mc.new_workspace(n, dev, a.dtype, update, b)
     res = mc.new_result(dev, 1)
     for _ in range(warmup):
-        mc.logdet_async(a, res, work, b=b)
+        mc.logdet_async(a, res, work, b=b, update=update)
     torch.cuda.synchronize()
     if profile:
         mc.profile_enable(True)
@@ -151,7 +159,7 @@ def timed(mc, torch, a, b, steps, warmup, stream, profile=False):
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
-        mc.logdet_async(a, res, work, b=b)
+        mc.logdet_async(a, res, work, b=b, update=update)
     e1.record(stream)
     torch.cuda.synchronize()
     prof = None
@@ -161,26 +169,145 @@ def timed(mc, torch, a, b, steps, warmup, stream, profile=False):
     return e0.elapsed_time(e1) / steps, mc.read_result(res)[0], prof
 
 
-def roofline_of(kind, p, workload, b):
+def roofline_of(kind, p, workload, b, prec="f64"):
     """Roofline entry for one timed kernel kind (p: library profile)."""
     if p.launches == 0 or p.elapsed_ms <= 0:
         return None
     avg_us = p.elapsed_ms * 1e3 / p.launches
     if kind == "update":
-        ach = p.alg_flops / (p.elapsed_ms * 1e-3) / 1e12
-        r = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFS,
-             "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFS}
+        peak, mult = mfma_peak(prec)
+        ach = mult * p.alg_flops / (p.elapsed_ms * 1e-3) / 1e12
+        r = {"bound": "mfma", "achieved": ach, "peak": peak,
+             "unit": "TFLOP/s", "frac": ach / peak}
     else:
         ach = p.alg_bytes / (p.elapsed_ms * 1e-3) / 1e9
         r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
     r["traffic"] = stored_traffic(kind, workload, b)
-    r.update({"kernel": KERNEL_NAME[kind], "launches": p.launches,
+    name = KERNEL_NAME[kind if kind != "update" or prec == "f64"
+                       else f"update_{prec}"]
+    r.update({"kernel": name, "launches": p.launches,
               "avg_launch_us": avg_us,
               "alg_bytes_per_launch": p.alg_bytes / p.launches,
               "alg_flops_per_launch": p.alg_flops / p.launches,
               "share_of_step": None})
     return r
+
+
+def gpu_gram(torch, dev):
+    """X^T X in FP64 on the GPU for the Wishart inputs (the draws are the
+    seeded host draws; only the product runs on the device)."""
+    def gram(x):
+        xd = torch.from_numpy(x).to(dev)
+        return torch.matmul(xd.t().contiguous(), xd).cpu().numpy()
+    return gram
+
+
+def cpu_baseline_batch(mats, target_s: float):
+    """The oracle (single thread) on the first members of the batch until
+    about target_s, scaled to the whole batch by sum n^3."""
+    from oracle import oracle as O
+
+    done, t_used = 0, 0.0
+    while done < len(mats) and t_used < target_s:
+        t0 = time.perf_counter()
+        O.slogdet(mats[done])
+        t_used += time.perf_counter() - t0
+        done += 1
+    w_all = sum(float(m.shape[0]) ** 3 for m in mats)
+    w_done = sum(float(m.shape[0]) ** 3 for m in mats[:done])
+    full = t_used * w_all / w_done
+    return {"value": len(mats) / full, "unit": "log-dets/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"first {done} of {len(mats)} matrices of the batch "
+                       f"({t_used:.1f} s on 1 core), scaled by sum n^3 to "
+                       f"the whole batch ({full:.1f} s)")}
+
+
+def mfma_peak(prec: str):
+    """(peak TFLOP/s, MFMA products per useful flop) of a precision."""
+    return {"f64": (FP64_PEAK_TFS, 1), "f32": (FP32_PEAK_TFS, 1),
+            "bf16x3": (BF16_PEAK_TFS, 3)}[prec]
+
+
+def run_batch(args, mc, torch, synth, spec, dev, stream):
+    """One persistent batched launch over the whole batch, captured in a
+    graph and replayed; the plain FP64 GPU path beside it, one call per
+    member."""
+    prec = args.precision
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    update = {"f64": "native", "f32": "f32", "bf16x3": "bf16x3"}[prec]
+    print(f"# generating {args.workload}", file=sys.stderr, flush=True)
+    sizes, mats = synth.make(args.workload, gram=gpu_gram(torch, dev))
+    devs = [torch.from_numpy(m).to(dev, dtype) for m in mats]
+    plan = mc.BatchedPlan(devs, b=-1, update=update)
+    plan.capture()
+    steps = args.steps if args.steps is not None else 20
+    warmup = args.warmup if args.warmup is not None else 2
+    for _ in range(warmup):
+        plan.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    got = plan.results()
+    flops = sum(2.0 * n ** 3 / 3.0 for n in sizes)
+    value = len(sizes) / (ms * 1e-3)
+
+    exp_path = os.path.join(ROOT, "tests", "golden", f"expected_{args.workload}.json")
+    worst, signs = None, None
+    if os.path.exists(exp_path):
+        with open(exp_path) as f:
+            exp = json.load(f)["f64" if prec == "f64" else "f32"]
+        worst = max(abs(g.logabsdet - e["logabsdet"]) / max(abs(e["logabsdet"]), 1.0)
+                    for g, e in zip(got, exp))
+        signs = all(g.sign == e["sign"] for g, e in zip(got, exp))
+    peak, mult = mfma_peak(prec)
+    ach = mult * flops / (ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": None,
+            "kernel": "batched_persistent (one launch for the whole batch)",
+            "launches": 1, "avg_launch_us": ms * 1e3,
+            "note": (f"achieved = {mult} x the useful 2n^3/3 flops per "
+                     "member over the graph replay (one persistent kernel)")}
+    out = {
+        "metric": METRIC, "value": value, "unit": "log-dets/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "batch": len(sizes),
+                   "n_min": min(sizes), "n_max": max(sizes),
+                   "precision": prec, "path": "batched", "graph": True},
+        "gflops": flops / (ms * 1e-3) / 1e9,
+        "rel_err_vs_oracle": worst, "sign_matches_oracle": signs,
+        "roofline": roof,
+    }
+    if not args.no_plain:
+        print("# plain FP64 GPU path, member by member", file=sys.stderr, flush=True)
+        a64 = [torch.from_numpy(m).to(dev) for m in mats]
+        work = mc.new_workspace(max(sizes), dev, torch.float64, "native", 0)
+        res = mc.new_result(dev, len(a64))
+        for a in a64[:2]:
+            mc.logdet_async(a, res[0:1], work, b=0)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i, a in enumerate(a64):
+            mc.logdet_async(a, res[i:i + 1], work, b=0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1)
+        out["plain_fp64_gpu"] = {"ms_per_batch": pms,
+                                 "value": len(a64) / (pms * 1e-3)}
+        out["speedup_vs_plain_fp64_gpu"] = pms / ms
+    if not args.no_cpu:
+        print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_batch(mats, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -210,28 +337,41 @@ def main():
                           "launches": 3}), flush=True)
         return
     spec = synth.CONFIGS[args.workload]
+    stream = torch.cuda.current_stream(dev)
+    if spec["kind"] == "wishart_batch":
+        run_batch(args, mc, torch, synth, spec, dev, stream)
+        return
     n = spec["n"]
+    prec = args.precision
+    update = {"f64": "native", "f32": "f32", "bf16x3": "bf16x3"}[prec]
     plain = args.path == "plain"
+    if plain and prec != "f64":
+        print(json.dumps({"error": "the plain path is FP64 only"}))
+        sys.exit(2)
     b = 0 if plain else args.b
     if b < 0:
         b = mc.default_panel(n)
     steps = args.steps if args.steps is not None else (3 if plain else 20)
     warmup = args.warmup if args.warmup is not None else 1
-    stream = torch.cuda.current_stream(dev)
 
     print(f"# generating {args.workload}", file=sys.stderr, flush=True)
-    a_np = synth.make(args.workload)
-    a = torch.from_numpy(a_np).to(dev)
+    if spec["kind"] == "wishart":
+        a_np = synth.make(args.workload, gram=gpu_gram(torch, dev))
+    else:
+        a_np = synth.make(args.workload)
+    a64 = torch.from_numpy(a_np).to(dev)
+    a = a64 if prec == "f64" else a64.to(torch.float32)
 
     if not plain:
         mc.lookahead_enable(args.lookahead == "on")
     print(f"# {args.path} b={b}: warmup {warmup}, timing {steps}",
           file=sys.stderr, flush=True)
-    ms_per_step, got, _ = timed(mc, torch, a, b, steps, warmup, stream)
+    ms_per_step, got, _ = timed(mc, torch, a, b, steps, warmup, stream,
+                                update=update)
     print(f"# kernel timing pass: {args.profile_steps} steps",
           file=sys.stderr, flush=True)
     prof_ms, _, prof = timed(mc, torch, a, b, args.profile_steps, 0, stream,
-                             profile=True)
+                             profile=True, update=update)
     value = 1000.0 / ms_per_step
     gflops = (2.0 * n ** 3 / 3.0) / (ms_per_step * 1e-3) / 1e9
 
@@ -241,16 +381,18 @@ def main():
                             f"expected_{args.workload}.json")
     if os.path.exists(exp_path):
         with open(exp_path) as f:
-            exp = json.load(f)["f64"]
-        rel_err = abs(got.logabsdet - exp["logabsdet"]) / max(
-            abs(exp["logabsdet"]), 1.0)
-        sign_ok = got.sign == exp["sign"]
+            allexp = json.load(f)
+        exp = allexp["f64"]
+        mine = allexp["f32"] if prec != "f64" else exp
+        rel_err = abs(got.logabsdet - mine["logabsdet"]) / max(
+            abs(mine["logabsdet"]), 1.0)
+        sign_ok = got.sign == mine["sign"]
 
     # roofline of the dominant kernel (largest timed share of the step)
     entries = {}
     for k in (["plain_step"] if plain else ["panel", "update"]):
         p = prof["update" if k == "plain_step" else k]
-        r = roofline_of(k, p, args.workload, b)
+        r = roofline_of(k, p, args.workload, b, prec)
         if r is not None:
             r["share_of_step"] = p.elapsed_ms / args.profile_steps / prof_ms
             r["timing_pass_ms_per_step"] = prof_ms
@@ -265,10 +407,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": (value * PAPER_BEST_N8000_S
                         if args.workload == "normal_n8000" else None),
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if prec == "f64" else "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n": n,
                    "dist": spec["kind"], "seed": spec.get("seed"),
-                   "path": args.path, "b": b,
+                   "path": args.path, "b": b, "precision": prec,
                    "lookahead": None if plain else args.lookahead},
         "gflops": gflops,
         "rel_err_vs_oracle": rel_err, "sign_matches_oracle": sign_ok,
@@ -279,7 +421,7 @@ def main():
     if not plain and not args.no_plain:
         print(f"# plain FP64 GPU path: {args.plain_steps} steps",
               file=sys.stderr, flush=True)
-        pms, pgot, pprof = timed(mc, torch, a, 0, args.plain_steps, 1, stream,
+        pms, pgot, pprof = timed(mc, torch, a64, 0, args.plain_steps, 1, stream,
                                  profile=True)
         p = pprof["update"]
         pach = p.alg_bytes / (p.elapsed_ms * 1e-3) / 1e9
