@@ -594,6 +594,9 @@ struct PanelXShared {
     double wmax[16];
     int wbad[16];
     unsigned long long wkey[16];
+    double piv_p;   // the published row's pivot (0 when the step failed)
+    double piv_vi;  // the published row's entry at its own position i
+    int piv_l;      // the pivot position (-1 when the step failed)
 };
 
 __device__ __forceinline__ double wave_max(double x)
@@ -661,7 +664,9 @@ __device__ __forceinline__ void panelx_apply(T (&x)[EPT], const T (&r)[EPT],
 // unfactored first (the stores drain while the pivot is searched), then the
 // pivot (largest |v| over positions >= i, ties to the smallest original
 // column id, Section 2.2), the column-id exchange, and the flag, which
-// carries the pivot position + 1.  ids[j - s0] is the original column id at
+// carries the pivot position + 1.  On return sm.piv_l / piv_p / piv_vi hold
+// the pivot position (-1 if the step failed), its value and the row's entry
+// at i, for the block's own next rows.  ids[j - s0] is the original column id at
 // position j.  Thread tid holds positions s0 + e*NT + tid; position tests
 // compare tid with wave-uniform bounds, so no per-entry index is kept in a
 // vector register (n <= 2^30: 32-bit indices).
@@ -674,8 +679,10 @@ __device__ __forceinline__ void panelx_publish(int n, int s0, int i, const T (&v
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     T* ri = w.W + (int64_t)i * w.ldw + s0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e)
+    for (int e = 0; e < EPT; ++e) {
         if (tid < n - s0 - e * NT) ri[e * NT + tid] = v[e];
+        if (tid == i - s0 - e * NT) sm.piv_vi = (double)v[e];
+    }
     // pass 1: the largest |v| and whether any entry is not finite
     double m = 0.0;
     bool bad = false;
@@ -726,11 +733,14 @@ __device__ __forceinline__ void panelx_publish(int n, int s0, int i, const T (&v
             for (int q = 1; q < NW; ++q) k = sm.wkey[q] < k ? sm.wkey[q] : k;
             const int slot = (int)(k & 0x7fffffffu);
             const int colid = (int)(k >> 32);
+            const double p = ((k >> 31) & 1u) ? -M : M;
             w.piv_pos[i] = slot;
-            w.piv_val[i] = ((k >> 31) & 1u) ? -M : M;
+            w.piv_val[i] = p;
             w.perm[slot] = ids[i - s0]; // exchange the column ids
             w.perm[i] = colid;
             sm.wkey[0] = (unsigned long long)(slot + 1);
+            sm.piv_l = slot;
+            sm.piv_p = p;
         }
     } else if (tid == 0) {
         w.piv_pos[i] = -1;
@@ -738,6 +748,8 @@ __device__ __forceinline__ void panelx_publish(int n, int s0, int i, const T (&v
         w.state->bad_step = i;
         w.state->status = st;
         sm.wkey[0] = 1;
+        sm.piv_l = -1;
+        sm.piv_p = 0.0;
     }
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0); // every store has reached L2
     __syncthreads();
@@ -771,104 +783,142 @@ blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        sh_slot = (e == x) ? atomicAdd(&w.claim[0], 1) : -1;
+        sh_slot = (e == x) ? 0 : -1;
     }
     __syncthreads();
-    const int slot = sh_slot;
-    if (slot < 0 || slot >= nslots) return;
+    if (sh_slot < 0) return;
     const __amdgpu_buffer_rsrc_t flags = l2_rsrc(w.stepflag, sizeof(int) * kMaxPanel);
     const __amdgpu_buffer_rsrc_t pivs = l2_rsrc(w.piv_pos, sizeof(int) * (int64_t)n);
     const __amdgpu_buffer_rsrc_t pvals = l2_rsrc(w.piv_val, sizeof(double) * (int64_t)n);
     const __amdgpu_buffer_rsrc_t stat = l2_rsrc(&w.state->status, sizeof(int));
-    // this block's copy of the column ids, from the snapshot the head step
-    // wrote (the live array changes while the panel runs); every step's
-    // exchange is then applied here as it is observed
-    for (int t = tid; t < n - s0; t += NT) sh_perm[t] = w.perm0[s0 + t];
-    int row[R]; // increasing; -1 once gone
-    int ilast = s0;
-    T v[R][EPT];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        row[q] = s0 + 1 + slot + q * nslots;
-        if (row[q] >= pend) row[q] = -1; // no row
-        else ilast = row[q];
-        const T* rq = w.W + (int64_t)(row[q] < 0 ? 0 : row[q]) * w.ldw + s0;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            v[q][e] = (row[q] >= 0 && tid < n - s0 - e * NT) ? rq[e * NT + tid] : T(0);
-    }
-    for (int s = s0; s < ilast; ++s) {
-        if (tid == 0) {
-            int f = 1;
-            if (s > s0) {
-                long spins = 0;
-                const uint64_t t0 = now_ticks();
-                while ((f = l2_poll(flags, s - s0)) == 0) {
-                    ++spins;
-                    if ((spins & 255) == 0) {
-                        if (now_ticks() - t0 > kWaitTicks) {
-                            w.state->status = kStatusAborted;
-                            break;
-                        }
-                        if (l2_poll(stat, 0) != kStatusOk) break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            sh_status = l2_poll(stat, 0);
-            sh_l = (s > s0) ? f - 1 : l2_load<int>(pivs, s);
-        }
+    for (;;) { // slots in increasing order until none is left
         __syncthreads();
-        if (sh_status != kStatusOk) return; // uniform across the block
-        const int l = __builtin_amdgcn_readfirstlane(sh_l);
-        const bool factored = (s == s0); // the head step's row is factored
-        const T* rs = w.W + (int64_t)s * w.ldw;
-        // the pivot row through a descriptor that starts at position s+1:
-        // offsets below it wrap to huge values and, like those at or past
-        // n, fail the range check and read as zero
-        const __amdgpu_buffer_rsrc_t rrow =
-            l2_rsrc(rs + s + 1, sizeof(T) * (int64_t)(n - s - 1));
-        T r[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) r[e] = l2_load<T>(rrow, s0 + e * NT + tid - s - 1);
-        T vs = T(0), ps = T(1);
-        if (!factored) {
-            vs = l2_load<T>(l2_rsrc(rs + s, sizeof(T)), 0);
-            ps = (T)l2_load<double>(pvals, s);
-        }
-        if (tid == 0 && !factored && l != s) { // step s exchanged l and s
-            const int a = sh_perm[s - s0];
-            sh_perm[s - s0] = sh_perm[l - s0];
-            sh_perm[l - s0] = a;
-        }
-        if (tid == (l - s0) % NT) { // owner of position l: the multipliers
-            const int el = (l - s0) / NT;
-#pragma unroll
-            for (int q = 0; q < R; ++q) sh_c[q] = pick<T, EPT>(v[q], el);
-        }
-        if (tid == (s - s0) % NT) { // owner of position s: the entries at s
-            const int es = (s - s0) / NT;
-#pragma unroll
-            for (int q = 0; q < R; ++q) sh_xs[q] = pick<T, EPT>(v[q], es);
-        }
+        if (tid == 0) sh_slot = atomicAdd(&w.claim[0], 1);
         __syncthreads();
-        // the row to publish next is always v[0] (a slot's rows go out in
-        // order): update it, publish it, then update the others
-        const bool pub = (row[0] == s + 1);
-        if (pub) {
-            const T c = sh_c[0];
-            panelx_apply<T, NT, EPT>(v[0], r, s0, s, l, c, factored ? c : c / ps,
-                                     sh_xs[0], factored, vs);
-            panelx_publish<T, NT, EPT>(n, s0, s + 1, v[0], sh_perm, sm, w);
-        }
+        const int slot = sh_slot;
+        if (slot >= nslots) return;
+        // this slot's rows: R consecutive panel rows, so it only ever waits
+        // for rows of lower slots, which were claimed (and so are running
+        // or done) before it
+        int row[R]; // increasing; -1 once gone
+        T v[R][EPT];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            if (row[q] <= s || (q == 0 && pub)) continue;
-            const T c = sh_c[q];
-            panelx_apply<T, NT, EPT>(v[q], r, s0, s, l, c, factored ? c : c / ps,
-                                     sh_xs[q], factored, vs);
+            row[q] = s0 + 1 + slot * R + q;
+            if (row[q] >= pend) row[q] = -1;
+            const T* rq = w.W + (int64_t)(row[q] < 0 ? 0 : row[q]) * w.ldw + s0;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                v[q][e] = (row[q] >= 0 && tid < n - s0 - e * NT) ? rq[e * NT + tid] : T(0);
         }
-        if (pub) {
+        // the block's copy of the column ids, from the snapshot the head
+        // step wrote (the live array changes while the panel runs); each
+        // later step's exchange is applied here as it is taken
+        for (int t = tid; t < n - s0; t += NT) sh_perm[t] = w.perm0[s0 + t];
+        // phase A: the steps before this slot's first row, whose pivot
+        // rows other blocks publish (the head step's row arrives factored)
+        for (int s = s0; s < row[0]; ++s) {
+            if (tid == 0) {
+                int f = 1;
+                if (s > s0) {
+                    long spins = 0;
+                    const uint64_t t0 = now_ticks();
+                    while ((f = l2_poll(flags, s - s0)) == 0) {
+                        ++spins;
+                        if ((spins & 255) == 0) {
+                            if (now_ticks() - t0 > kWaitTicks) {
+                                w.state->status = kStatusAborted;
+                                break;
+                            }
+                            if (l2_poll(stat, 0) != kStatusOk) break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                sh_status = l2_poll(stat, 0);
+                sh_l = (s > s0) ? f - 1 : l2_load<int>(pivs, s);
+            }
+            __syncthreads();
+            if (sh_status != kStatusOk) return; // uniform across the block
+            const int l = __builtin_amdgcn_readfirstlane(sh_l);
+            const bool factored = (s == s0);
+            const T* rs = w.W + (int64_t)s * w.ldw;
+            // the pivot row through a descriptor that starts at position
+            // s+1: offsets below it wrap to huge values and, like those at
+            // or past n, fail the range check and read as zero
+            const __amdgpu_buffer_rsrc_t rrow =
+                l2_rsrc(rs + s + 1, sizeof(T) * (int64_t)(n - s - 1));
+            T r[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) r[e] = l2_load<T>(rrow, s0 + e * NT + tid - s - 1);
+            T vs = T(0), ps = T(1);
+            if (!factored) {
+                vs = l2_load<T>(l2_rsrc(rs + s, sizeof(T)), 0);
+                ps = (T)l2_load<double>(pvals, s);
+            }
+            if (tid == 0 && !factored && l != s) { // step s exchanged l and s
+                const int a = sh_perm[s - s0];
+                sh_perm[s - s0] = sh_perm[l - s0];
+                sh_perm[l - s0] = a;
+            }
+            if (tid == (l - s0) % NT) { // owner of position l: multipliers
+                const int el = (l - s0) / NT;
+#pragma unroll
+                for (int q = 0; q < R; ++q) sh_c[q] = pick<T, EPT>(v[q], el);
+            }
+            if (tid == (s - s0) % NT) { // owner of position s
+                const int es = (s - s0) / NT;
+#pragma unroll
+                for (int q = 0; q < R; ++q) sh_xs[q] = pick<T, EPT>(v[q], es);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if (row[q] < 0) continue;
+                const T c = sh_c[q];
+                panelx_apply<T, NT, EPT>(v[q], r, s0, s, l, c, factored ? c : c / ps,
+                                         sh_xs[q], factored, vs);
+            }
+        }
+        // phase B: this slot's rows in order; each is final once the
+        // previous one is applied, which the block does from registers
+        for (;;) {
+            const int i = row[0];
+            panelx_publish<T, NT, EPT>(n, s0, i, v[0], sh_perm, sm, w);
+            const int l = sm.piv_l;
+            if (l < 0) return; // the step failed; its status is published
+            const int next = (R > 1) ? row[R > 1 ? 1 : 0] : -1;
+            if (next < 0) break;
+            const T p = (T)sm.piv_p, vi = (T)sm.piv_vi;
+            if (tid == 0 && l != i) { // step i exchanged l and i
+                const int a = sh_perm[i - s0];
+                sh_perm[i - s0] = sh_perm[l - s0];
+                sh_perm[l - s0] = a;
+            }
+            if (tid == (l - s0) % NT) {
+                const int el = (l - s0) / NT;
+#pragma unroll
+                for (int q = 1; q < R; ++q) sh_c[q] = pick<T, EPT>(v[q], el);
+            }
+            if (tid == (i - s0) % NT) {
+                const int ei = (i - s0) / NT;
+#pragma unroll
+                for (int q = 1; q < R; ++q) sh_xs[q] = pick<T, EPT>(v[q], ei);
+            }
+            __syncthreads();
+            T r[EPT]; // the published row right of i, zero elsewhere
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int base = s0 + e * NT;
+                r[e] = (tid > i - base && tid < n - base) ? v[0][e] : T(0);
+            }
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                if (row[q] < 0) continue;
+                const T c = sh_c[q];
+                panelx_apply<T, NT, EPT>(v[q], r, s0, i, l, c, c / p, sh_xs[q],
+                                         false, vi);
+            }
 #pragma unroll
             for (int q = 0; q + 1 < R; ++q) {
                 row[q] = row[q + 1];
@@ -937,7 +987,7 @@ static void launch_panel_x(int64_t n, int64_t s0, int64_t pend,
 {
     const int rows = (int)(pend - 1 - s0);
     const int R = (rows + 31) / 32; // 1 .. 4 (rows <= 127)
-    const int nslots = (rows + R - 1) / R;
+    const int nslots = (rows + R - 1) / R; // slot q: rows s0+1+qR ..
     const dim3 grid((unsigned)(8 * nslots)), block(NT);
     if (R == 1)
         hipLaunchKernelGGL((blk_panel_x<T, NT, EPT, 1>), grid, block, 0, stream, n, s0, pend, nslots, w);
