@@ -1491,8 +1491,9 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                            dim3((unsigned)((rows + kTrsmRows - 1) / kTrsmRows)),
                            dim3(kBlkThreads), trsm_mfma_lds_bytes<T>(nb), stream,
                            n, s0, nb, wk);
-        // the next panel's rows first, on the caller's stream
-        const int64_t next = std::min<int64_t>(b, rows);
+        // with a side stream: the next panel's rows first, on the caller's
+        // stream, the rest beside the next panel; else one launch for all
+        const int64_t next = la ? std::min<int64_t>(b, rows) : rows;
         hipError_t e = trailing(wk, update, s0, nb, pend, next, n, stream);
         if (e != hipSuccess) return e;
         hipStream_t rest = stream;

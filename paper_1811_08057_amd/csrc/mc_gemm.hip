@@ -25,9 +25,11 @@ constexpr int kGemmThreads = 256;
 // registers while chunk c feeds the matrix cores, then parked in the other
 // LDS buffer; one barrier per chunk.  (The FP64 matrix cores reach their
 // peak only with two or more wavefronts issuing per SIMD, hence 8-wave
-// blocks for the large tile.)
+// blocks for the large tile.)  The second launch bound is in wavefronts
+// per SIMD: WGM*WGN/2 keeps two blocks resident per compute unit (for the
+// 8-wave tile: at most 128 VGPRs).
 template <class P, int WGM, int WGN, int TM, int TN>
-__global__ void __launch_bounds__(64 * WGM * WGN, 2)
+__global__ void __launch_bounds__(64 * WGM * WGN, (WGM * WGN) / 2)
 gemm_scalar(GemmArgs<typename P::T> g)
 {
     using T = typename P::T;
