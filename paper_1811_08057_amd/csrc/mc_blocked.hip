@@ -1097,9 +1097,19 @@ blk_fixup_x(int64_t n, int64_t s0, int nb, BlkWork<T> w)
         const int64_t l = w.piv_pos[u];
         const T vu = row[u];
         __syncthreads(); // every thread has vu before position u is written
-        for (int64_t j = u + threadIdx.x; j < n; j += kBlkThreads) {
-            const T x = row[j];
-            row[j] = (j == u) ? p : ((j == l) ? vu : x) / p;
+        constexpr int U8 = 8; // entries per thread per pass, all loads first
+        for (int64_t j0 = u + threadIdx.x; j0 < n; j0 += (int64_t)U8 * kBlkThreads) {
+            T x[U8];
+#pragma unroll
+            for (int q = 0; q < U8; ++q) {
+                const int64_t j = j0 + (int64_t)q * kBlkThreads;
+                x[q] = j < n ? row[j] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < U8; ++q) {
+                const int64_t j = j0 + (int64_t)q * kBlkThreads;
+                if (j < n) row[j] = (j == u) ? p : ((j == l) ? vu : x[q]) / p;
+            }
         }
     }
     __syncthreads(); // the factored row (and lp) is visible to the block
@@ -1142,9 +1152,17 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
             w.moved[t] = (int)d;
         }
     }
-    // diagonal-block inverses: column c of block J solves U_JJ x = e_c
+    // diagonal-block inverses: column c of block J solves U_JJ x = e_c,
+    // with the blocks staged in LDS first (one coalesced read)
     const int nblk = (nb + 15) / 16;
     const T* U = w.W + s0 * w.ldw + s0;
+    __shared__ T Ud[kMaxPanel / 16][16][17];
+    for (int e = tid; e < nblk * 256; e += kBlkThreads) {
+        const int J = e >> 8, r = (e >> 4) & 15, v = e & 15;
+        const int pr = 16 * J + r, pv = 16 * J + v;
+        Ud[J][r][v] = (pv < nb && pr < nb) ? U[(int64_t)pr * w.ldw + pv] : T(0);
+    }
+    __syncthreads();
     for (int e = tid; e < nblk * 16; e += kBlkThreads) {
         const int J = e >> 4, c = e & 15;
         T x[16];
@@ -1157,9 +1175,7 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
 #pragma unroll
             for (int v = r + 1; v < 16; ++v) {
                 if (v > c) break;
-                const int pr = 16 * J + r, pv = 16 * J + v;
-                const T u = (pv < nb) ? U[(int64_t)pr * w.ldw + pv] : T(0);
-                sum = fma(u, x[v], sum);
+                sum = fma(Ud[J][r][v], x[v], sum);
             }
             x[r] = -sum;
         }
@@ -1185,20 +1201,33 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
     if (w.state->status != kStatusOk) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     T* X = reinterpret_cast<T*>(smem_raw) + wid * 16 * xld;
+    __shared__ int src_sh[kMaxPanel];
     const int64_t pend = s0 + nb;
     const int64_t i0 = pend + (int64_t)blockIdx.x * kTrsmRows + wid * 16;
     const T* __restrict__ W = w.W;
     const int64_t ldw = w.ldw;
     const T* U = W + s0 * ldw + s0;
     const int cin = lane & 15, kl = lane >> 4;
-    for (int J = 0; J < nblk; ++J) {
+    for (int t = tid; t < nb; t += kBlkThreads) src_sh[t] = w.srcp[t];
+    __syncthreads();
+    // every gathered entry of A21 first (one memory latency for all blocks)
+    T g[kMaxPanel / 16][4];
+#pragma unroll
+    for (int J = 0; J < kMaxPanel / 16; ++J) {
         const int t = 16 * J + cin;
-        typename P::Acc acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t row = i0 + P::drow(lane, r);
-            acc[r] = (row < n && t < nb) ? W[row * ldw + w.srcp[t]] : T(0);
+            g[J][r] = (J < nblk && row < n && t < nb) ? W[row * ldw + src_sh[t]] : T(0);
         }
+    }
+#pragma unroll
+    for (int J = 0; J < kMaxPanel / 16; ++J) {
+        if (J >= nblk) break;
+        const int t = 16 * J + cin;
+        typename P::Acc acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = g[J][r];
         for (int K = 0; K < J; ++K) {
 #pragma unroll
             for (int kq = 0; kq < 4; ++kq) {
