@@ -1208,12 +1208,45 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
     const int64_t ldw = w.ldw;
     const T* U = W + s0 * ldw + s0;
     const int cin = lane & 15, kl = lane >> 4;
+    // U11's strictly upper 16x16 blocks (K < J at tri(K, J) = J(J-1)/2 + K)
+    // and the inverted diagonal blocks, both in LDS: the solve's chain then
+    // waits on no global load.
+    constexpr int kMaxBlk = kMaxPanel / 16;
+    constexpr int kMaxTri = kMaxBlk * (kMaxBlk - 1) / 2;
+    static_assert(kBlkThreads == 256, "one 16x16 block element per thread");
+    const int ntri = nblk * (nblk - 1) / 2;
+    T* Ub = reinterpret_cast<T*>(smem_raw) + kTrsmRows * xld;
+    T* Dv = Ub + ntri * 256;
     for (int t = tid; t < nb; t += kBlkThreads) src_sh[t] = w.srcp[t];
+    {
+        const int er = tid >> 4, ec = tid & 15;
+        T st[kMaxTri + kMaxBlk];
+        int bi = 0;
+#pragma unroll
+        for (int J = 1; J < kMaxBlk; ++J)
+#pragma unroll
+            for (int K = 0; K < J; ++K, ++bi) {
+                const int t = 16 * J + ec;
+                st[bi] = (J < nblk && t < nb) ? U[(int64_t)(16 * K + er) * ldw + t] : T(0);
+            }
+#pragma unroll
+        for (int J = 0; J < kMaxBlk; ++J)
+            st[kMaxTri + J] = J < nblk ? w.dinv[J * 256 + tid] : T(0);
+        bi = 0;
+#pragma unroll
+        for (int J = 1; J < kMaxBlk; ++J)
+#pragma unroll
+            for (int K = 0; K < J; ++K, ++bi)
+                if (J < nblk) Ub[bi * 256 + tid] = st[bi];
+#pragma unroll
+        for (int J = 0; J < kMaxBlk; ++J)
+            if (J < nblk) Dv[J * 256 + tid] = st[kMaxTri + J];
+    }
     __syncthreads();
     // every gathered entry of A21 first (one memory latency for all blocks)
-    T g[kMaxPanel / 16][4];
+    T g[kMaxBlk][4];
 #pragma unroll
-    for (int J = 0; J < kMaxPanel / 16; ++J) {
+    for (int J = 0; J < kMaxBlk; ++J) {
         const int t = 16 * J + cin;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1233,7 +1266,7 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
             for (int kq = 0; kq < 4; ++kq) {
                 const int k = 16 * K + 4 * kq + kl; // k < 16 J <= t
                 const T a = -X[cin * xld + k];
-                const T b = (t < nb) ? U[(int64_t)k * ldw + t] : T(0);
+                const T b = Ub[(J * (J - 1) / 2 + K) * 256 + (4 * kq + kl) * 16 + cin];
                 acc = P::mma(a, b, acc);
             }
         }
@@ -1244,7 +1277,7 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) {
             const T a = X[cin * xld + 16 * J + 4 * kq + kl];
-            const T b = w.dinv[(J * 16 + 4 * kq + kl) * 16 + cin];
+            const T b = Dv[(J * 16 + 4 * kq + kl) * 16 + cin];
             x = P::mma(a, b, x);
         }
         __syncthreads();
@@ -1371,7 +1404,9 @@ template <typename T>
 static size_t trsm_mfma_lds_bytes(int nb)
 {
     const int nblk = (nb + 15) / 16;
-    return sizeof(T) * (size_t)(kTrsmRows) * (size_t)(nblk * 16 + 1);
+    const int ntri = nblk * (nblk - 1) / 2; // strictly upper 16x16 blocks of U11
+    return sizeof(T) * ((size_t)(kTrsmRows) * (size_t)(nblk * 16 + 1) +
+                        (size_t)(ntri + nblk) * 256);
 }
 
 // ---- one-panel lookahead ----
