@@ -930,6 +930,24 @@ blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
     }
 }
 
+// Undo the exchanges of panel steps hi-1 down to lo (step t exchanged
+// positions s0+t and lp[t]) on Q positions per lane at once.  lp0 and lp1
+// hold lp[lane] and lp[lane + 64]; every step's partner is read from them
+// with readlane (lo, hi and the step index are wave-uniform).
+template <int Q>
+__device__ __forceinline__ void undo_exchanges(int (&pos)[Q], int s0, int lo,
+                                               int hi, int lp0, int lp1)
+{
+    for (int t = hi - 1; t >= lo; --t) {
+        const int b = t < kWave ? __builtin_amdgcn_readlane(lp0, t)
+                                : __builtin_amdgcn_readlane(lp1, t - kWave);
+        const int a = s0 + t;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            pos[q] = pos[q] == a ? b : (pos[q] == b ? a : pos[q]);
+    }
+}
+
 // Panel rows published before the last steps: apply the exchanges of the
 // steps after their own (one wavefront per row; sources found by undoing
 // the exchanges in reverse, every value read before any is written).
@@ -938,34 +956,27 @@ __device__ void panel_row_fixup(BlkWork<T>& w, int64_t s0, int nb, int64_t u,
                                 const int* lp)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t pend = s0 + nb;
+    const int rel = (int)(u - s0);
     T* row = w.W + u * w.ldw;
-    T val[4];
-    int64_t dst[4];
+    const int lp0 = lane < nb ? lp[lane] : 0;
+    const int lp1 = lane + kWave < nb ? lp[lane + kWave] : 0;
+    int d[4], pos[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int e = lane + q * kWave; // 0..255: steps u+1.. and their l
-        dst[q] = -1;
-        const int64_t s = u + 1 + (e >> 1);
-        if (s >= pend) continue;
-        const int64_t d = (e & 1) ? lp[s - s0] : s;
-        int64_t pos = d;
-        for (int64_t t = pend - 1; t > u; --t) {
-            const int64_t a = t, b = lp[t - s0];
-            if (pos == a)
-                pos = b;
-            else if (pos == b)
-                pos = a;
-        }
-        if (pos != d) {
-            dst[q] = d;
-            val[q] = row[pos];
-        }
+        const int t = rel + 1 + (e >> 1);
+        d[q] = t < nb ? ((e & 1) ? lp[t] : (int)s0 + t) : -1;
+        pos[q] = d[q];
     }
+    undo_exchanges<4>(pos, (int)s0, rel + 1, nb, lp0, lp1);
+    T val[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (d[q] >= 0 && pos[q] != d[q]) val[q] = row[pos[q]];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        if (dst[q] >= 0) row[dst[q]] = val[q];
+        if (d[q] >= 0 && pos[q] != d[q]) row[d[q]] = val[q];
 }
 
 // Elements per thread for a row of `width` active entries, or 0 when the
@@ -1065,6 +1076,7 @@ template <typename T>
 __device__ void panel_row_fixup(BlkWork<T>& w, int64_t s0, int nb, int64_t u,
                                 const int* lp);
 
+
 // Fix-up of the panel rows published by the persistent panel kernel (four
 // rows per block).  Runs before blk_perm, which reads the fixed rows (U11).
 template <typename T>
@@ -1097,7 +1109,7 @@ blk_fixup_x(int64_t n, int64_t s0, int nb, BlkWork<T> w)
         const int64_t l = w.piv_pos[u];
         const T vu = row[u];
         __syncthreads(); // every thread has vu before position u is written
-        constexpr int U8 = 8; // entries per thread per pass, all loads first
+        constexpr int U8 = 16; // entries per thread per pass, all loads first
         for (int64_t j0 = u + threadIdx.x; j0 < n; j0 += (int64_t)U8 * kBlkThreads) {
             T x[U8];
 #pragma unroll
@@ -1133,23 +1145,23 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
     for (int t = tid; t < nb; t += kBlkThreads) lp[t] = w.piv_pos[s0 + t];
     __syncthreads();
     const int64_t pend = s0 + nb;
-    auto trace = [&](int64_t d) -> int {
-        int64_t pos = d;
-        for (int u = nb - 1; u >= 0; --u) {
-            const int64_t a = s0 + u, b = lp[u];
-            if (pos == a)
-                pos = b;
-            else if (pos == b)
-                pos = a;
-        }
-        return (int)pos;
-    };
-    for (int t = tid; t < nb; t += kBlkThreads) {
-        w.srcp[t] = trace(s0 + t);
-        const int64_t d = lp[t];
-        if (d >= pend) {
-            w.colsrc[d] = trace(d);
-            w.moved[t] = (int)d;
+    static_assert(kMaxPanel <= 2 * kWave, "partners held in two registers");
+    {
+        const int lane = tid & (kWave - 1);
+        const int lp0 = lane < nb ? lp[lane] : 0;
+        const int lp1 = lane + kWave < nb ? lp[lane + kWave] : 0;
+        // destinations s0+t and lp[t], traced together; every lane runs the
+        // trace (readlane reads lanes that a branch would switch off)
+        const int t = tid < nb ? tid : 0;
+        const int d = lp[t];
+        int pos[2] = {(int)s0 + t, d};
+        undo_exchanges<2>(pos, (int)s0, 0, nb, lp0, lp1);
+        if (tid < nb) {
+            w.srcp[tid] = pos[0];
+            if (d >= pend) {
+                w.colsrc[d] = pos[1];
+                w.moved[tid] = d;
+            }
         }
     }
     // diagonal-block inverses: column c of block J solves U_JJ x = e_c,
@@ -1257,7 +1269,6 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
 #pragma unroll
     for (int J = 0; J < kMaxPanel / 16; ++J) {
         if (J >= nblk) break;
-        const int t = 16 * J + cin;
         typename P::Acc acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = g[J][r];
