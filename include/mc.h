@@ -236,6 +236,20 @@ mc_status mc_autotune_batched(int dtype, int update, int64_t n_max_tune,
 int mc_lookahead_enable(int on);
 
 /*
+ * Blocked path: choice of panel kernel for panels whose active width
+ * (n minus the panel's first step) is at most 8192 (Sections 2.2-2.4 on the
+ * panel's rows).  On (the default): one kernel per panel on the compute
+ * units of one XCD, each holding a slice of the panel's columns for all of
+ * its rows; a step exchanges only a pivot candidate and one column of
+ * multipliers per unit.  Off: the row-per-block panel kernels.  Both give
+ * the same pivots and the same factors up to rounding order.  Lookahead
+ * mode always uses the row-per-block kernels (the column-split kernel needs
+ * its blocks resident together).  Returns the previous setting (1 on,
+ * 0 off).  Process-wide; not synchronised with calls in flight.
+ */
+int mc_split_panel_enable(int on);
+
+/*
  * Optional timing of the kernels that dominate a call, in two kinds:
  *
  * MC_PROF_UPDATE  the condensation update.  Plain path: the whole run of

@@ -36,7 +36,8 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_tune_set", "mc_autotune_workspace", "mc_autotune_batched",
            "mc_last_hip_error", "mc_logdet_factor_workspace",
            "mc_logdet_factor", "mc_logdet_backward_workspace",
-           "mc_logdet_backward", "mc_lookahead_enable", "mc_default_panel")
+           "mc_logdet_backward", "mc_lookahead_enable", "mc_default_panel",
+           "mc_split_panel_enable")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -79,6 +80,8 @@ def lib() -> ctypes.CDLL:
     L.mc_default_panel.restype = ctypes.c_int64
     L.mc_lookahead_enable.argtypes = [ctypes.c_int]
     L.mc_lookahead_enable.restype = ctypes.c_int
+    L.mc_split_panel_enable.argtypes = [ctypes.c_int]
+    L.mc_split_panel_enable.restype = ctypes.c_int
     L.mc_profile_enable.argtypes = [ctypes.c_int]
     L.mc_profile_enable.restype = ctypes.c_int
     L.mc_profile_read.argtypes = [ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64), dp, dp]
@@ -217,6 +220,13 @@ def lookahead_enable(on: bool = True) -> bool:
     kernel on the caller's stream (the default); returns the previous
     setting."""
     return bool(lib().mc_lookahead_enable(1 if on else 0))
+
+
+def split_panel_enable(on: bool = True) -> bool:
+    """Blocked panels up to 8192 wide on the column-split kernel (the
+    default) or on the row-per-block kernels; returns the previous
+    setting."""
+    return bool(lib().mc_split_panel_enable(1 if on else 0))
 
 
 def profile_enable(on: bool = True) -> None:

@@ -153,6 +153,8 @@ static size_t blocked_bytes(int64_t n, int dtype, int64_t b, bool with_w)
     t += align_up(elem * (size_t)kMaxPanel * 16, kAlign);       // dinv
     t += align_up(sizeof(int) * (size_t)kMaxPanel, kAlign);     // stepflag
     t += align_up(2 * sizeof(int), kAlign);                     // claim
+    t += align_up(sizeof(unsigned long long) * 4 * kSplitSlices, kAlign); // xrec
+    t += align_up(elem * 2 * kSplitSlices * (size_t)kMaxPanel, kAlign);  // xcol
     t += align_up(sizeof(DevState), kAlign);
     return t;
 }
@@ -191,6 +193,9 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b, bool with_w)
     w.dinv = reinterpret_cast<T*>(take(sizeof(T) * (size_t)kMaxPanel * 16));
     w.stepflag = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.claim = reinterpret_cast<int*>(take(2 * sizeof(int)));
+    w.xrec = reinterpret_cast<unsigned long long*>(
+        take(sizeof(unsigned long long) * 4 * kSplitSlices));
+    w.xcol = reinterpret_cast<T*>(take(sizeof(T) * 2 * kSplitSlices * (size_t)kMaxPanel));
     w.state = reinterpret_cast<DevState*>(take(sizeof(DevState)));
     return w;
 }
@@ -233,6 +238,8 @@ extern "C" int mc_lookahead_enable(int on)
     g_lookahead_on = on != 0;
     return prev;
 }
+
+extern "C" int mc_split_panel_enable(int on) { return split_panel_set(on); }
 
 extern "C" mc_status mc_profile_enable(int on)
 {

@@ -28,6 +28,7 @@
 //   blk_trsm_mfma  L21 = gather(A21) * U11^{-1} on the matrix cores
 //   gemm       A22 <- gather(A22) - L21 * U12    (mc_gemm.hip)
 #include <algorithm>
+#include <type_traits>
 #include <mutex>
 
 #include "mc_device.h"
@@ -58,9 +59,14 @@ blk_init(const T* __restrict__ A, int64_t lda, int64_t n, BlkWork<T> w)
             w.moved[t] = -1;
             w.moved_b[t] = -1;
         }
+        // no candidate record of an earlier factorisation may pass for one
+        // of this one
+        for (int t = threadIdx.x; t < 4 * kSplitSlices; t += kBlkThreads) w.xrec[t] = 0;
         if (threadIdx.x == 0) {
             w.state->status = kStatusOk;
             w.state->bad_step = 0;
+            w.claim[0] = 0;
+            w.claim[1] = -1;
         }
     }
 }
@@ -930,6 +936,440 @@ blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
     }
 }
 
+// ---- column-split panel (one XCD) ----
+//
+// For panels at most kSplitSlices * 256 positions wide.  P blocks on one
+// XCD split the panel's positions into slices of CP = 8 * CPW columns and
+// keep their slice of all nb panel rows in registers for the whole panel:
+// wave v holds columns v*CPW .. v*CPW+CPW-1 of the slice, lane L the rows L
+// and L + 64.  Columns are never moved in memory: each keeps its original
+// id and tracks its current position, and the exchange of a step (the pivot
+// column and the column at the step's own position, Section 2.4) only swaps
+// two positions.  Step k (row k of the panel, absolute step s = s0 + k):
+//   1. every block applies step k-1 to the half of its rows that holds row
+//      k and finds its best entry of row k (largest |a|, ties to the
+//      smallest original id, Section 2.2);
+//   2. the wave holding that column posts it: the column's entries of the
+//      panel rows (with step k-1 applied), then one 16-byte record
+//      {|a| | generation bit, tag | sign | non-finite | id | position};
+//   3. every block reads the P records, takes the same winner, reads the
+//      winner's column c and keeps c_i / p as the multipliers of step k;
+//      the winning column retires (its entries below row k are the
+//      multipliers of Figure 6 step 4.8 and stay as they are);
+//   4. the rest of step k-1 (the other half of the rows) is applied while
+//      the records are awaited.
+// The update of an active column j is a_ij <- a_ij - (c_i / p) a_kj for the
+// rows i > k (Eq. 2/3 with the factored pivot row written out).  After the
+// last step every block writes its slice at the columns' final positions:
+// row i divided by its pivot at the columns that were still active at step
+// i (the factored rows of Section 2.3), the pivot itself and the
+// multipliers as they are.  All P blocks must be resident together (one
+// per compute unit of the XCD); every wait is bounded.
+
+constexpr int kSplitThreads = 512;
+constexpr int kSplitWaves = kSplitThreads / kWave;
+constexpr int kSplitNone = 0x7fffffff; // a column no step of the panel took
+
+static bool g_split_on = true;
+
+int split_panel_set(int on)
+{
+    const int prev = g_split_on ? 1 : 0;
+    g_split_on = on != 0;
+    return prev;
+}
+
+// Largest |a| first, then the smaller key (original id in the high word).
+__device__ __forceinline__ void split_take(uint64_t& a, uint64_t& k, uint64_t oa,
+                                           uint64_t ok)
+{
+    const bool t = oa > a || (oa == a && ok < k);
+    a = t ? oa : a;
+    k = t ? ok : k;
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x, uint64_t ident)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)ident, (int)(uint32_t)x,
+                                               CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(ident >> 32),
+                                               (int)(uint32_t)(x >> 32), CTRL,
+                                               ROWMASK, 0xf, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void best_step(uint64_t& a, uint64_t& k)
+{
+    const uint64_t oa = dpp64<CTRL, ROWMASK>(a, 0ull);
+    const uint64_t ok = dpp64<CTRL, ROWMASK>(k, ~0ull);
+    split_take(a, k, oa, ok);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The best (a, k) over the 64 lanes, in every lane: row shifts 1, 2, 4, 8
+// leave each row's best in its lane 15, the two row broadcasts carry them
+// to lane 63.  Called with every lane active.
+__device__ __forceinline__ void wave_best(uint64_t& a, uint64_t& k)
+{
+    best_step<0x111, 0xf>(a, k); // row_shr:1
+    best_step<0x112, 0xf>(a, k); // row_shr:2
+    best_step<0x114, 0xf>(a, k); // row_shr:4
+    best_step<0x118, 0xf>(a, k); // row_shr:8
+    best_step<0x142, 0xa>(a, k); // row_bcast:15
+    best_step<0x143, 0xc>(a, k); // row_bcast:31
+    a = readlane64(a, 63);
+    k = readlane64(k, 63);
+}
+
+// Plain buffer access of the panel rows (voffset per lane, soffset uniform).
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, int voff,
+                                                  int soff)
+{
+    typedef unsigned int v2u32 __attribute__((__vector_size__(8)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, v), r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, int voff,
+                                                 int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+template <typename T, int CPW>
+static size_t split_lds_bytes()
+{
+    return sizeof(T) * (size_t)kSplitWaves * 64 * (CPW + 1);
+}
+
+template <typename T, int CPW>
+__global__ void __launch_bounds__(kSplitThreads)
+blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
+{
+    constexpr int CP = kSplitWaves * CPW; // columns per slice
+    constexpr int TBLD = CPW + 1;
+    extern __shared__ unsigned char smem_raw[];
+    T* tb = reinterpret_cast<T*>(smem_raw); // [wave][64][TBLD] transposes
+    __shared__ T prow[2][CP];               // row k of the slice, by step parity
+    __shared__ T mult[2][kMaxPanel];        // multipliers c_i / p, by step parity
+    __shared__ double pv[kMaxPanel];        // pivot of each step
+    __shared__ int pl[kMaxPanel];           // pivot position of each step
+    __shared__ int cpos[CP], cstep[CP], cid[CP];
+    __shared__ int sh_slice, sh_st, sh_ws, sh_cl;
+
+    const int n = (int)n64, s0 = (int)s064, width = n - s0;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (tid == 0) {
+        // block 0 publishes its XCD; blocks elsewhere leave, the others
+        // take slices from a counter in that XCD's L2
+        const int x = xcc_id();
+        int e = x;
+        if (w.state->status != kStatusOk) {
+            e = -1;
+        } else if (blockIdx.x == 0) {
+            st_agent(&w.claim[1], x);
+        } else {
+            const uint64_t t0 = now_ticks();
+            while ((e = ld_agent(&w.claim[1])) < 0) {
+                if (now_ticks() - t0 > kWaitTicks) {
+                    st_agent(&w.state->status, (int)kStatusAborted);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        sh_slice = (e == x) ? atomicAdd(&w.claim[0], 1) : -1;
+    }
+    __syncthreads();
+    const int slice = sh_slice;
+    if (slice < 0 || slice >= nslices) return;
+
+    T* __restrict__ W = w.W;
+    const int64_t ldw = w.ldw;
+    const int cbase = slice * CP + wv * CPW; // first column of this wave (from s0)
+    for (int t = tid; t < CP; t += kSplitThreads) {
+        const int col = slice * CP + t;
+        const bool ok = col < width;
+        cpos[t] = ok ? s0 + col : -1;
+        cstep[t] = ok ? kSplitNone : -1; // active at step k: cstep >= k
+        cid[t] = ok ? w.perm[s0 + col] : 0x7fffffff;
+        prow[0][t] = prow[1][t] = T(0);
+    }
+    for (int t = tid; t < kMaxPanel; t += kSplitThreads) mult[0][t] = mult[1][t] = T(0);
+
+    // the slice's rows, loaded coalesced and transposed through LDS.  One
+    // buffer descriptor covers the panel rows (rows past nb read as zero);
+    // lane L reads column L % CPW of rows L / CPW + RS u (RS rows a load).
+    constexpr int RS = kWave / CPW;
+    const int c_l = lane % CPW, r_l = lane / CPW;
+    const bool col_ok = cbase + c_l < width;
+    const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+        W + (int64_t)s0 * ldw, 0, (int)(sizeof(T) * (int64_t)nb * ldw), 0x00020000);
+    const int row_bytes = (int)(sizeof(T) * ldw);
+    T x[2][CPW];
+    T* tw = tb + wv * 64 * TBLD;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int voff = r_l * row_bytes + (int)sizeof(T) * (s0 + (col_ok ? cbase + c_l : 0));
+        T t[CPW];
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) {
+            const T v = buf_load<T>(prs, voff, (64 * h + RS * u) * row_bytes);
+            t[u] = col_ok ? v : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) tw[(r_l + RS * u) * TBLD + c_l] = t[u];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) x[h][c] = tw[lane * TBLD + c];
+    }
+
+    const __amdgpu_buffer_rsrc_t stat = l2_rsrc(&w.state->status, sizeof(int));
+    // One step (row k in half H of the lanes' rows); false once the panel
+    // stops (a singular or non-finite pivot row, or an aborted wait).
+    auto step = [&](auto hc, int k) -> bool {
+        constexpr int H = decltype(hc)::value;
+        const int s = s0 + k, b = s & 1, pb = b ^ 1;
+        // 1. step k-1 on the half holding row k (a retired column is
+        //    updated too: only its rows up to its own step are kept, and
+        //    its multipliers went to W when it retired); the lane holding
+        //    row k posts the row
+        {
+            const T m = mult[pb][64 * H + lane];
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+                x[H][c] = fma(-m, prow[pb][wv * CPW + c], x[H][c]);
+        }
+        if (lane == (k & 63)) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) prow[b][wv * CPW + c] = x[H][c];
+        }
+        __syncthreads();
+        // the block's candidate, reduced by every wave alike
+        uint64_t a = 0, key = ~0ull;
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < CP / kWave; ++q) {
+            const int cl = lane + kWave * q;
+            if (cstep[cl] >= k) { // active (the step retiring it writes k)
+                const T v = prow[b][cl];
+                const double av = fabs((double)v);
+                if (!isfinite(av)) {
+                    bad = true;
+                } else {
+                    const uint64_t kk = ((uint64_t)(uint32_t)cid[cl] << 32) |
+                                        ((uint64_t)(v < T(0)) << 31) | (uint64_t)cl;
+                    split_take(a, key, (uint64_t)__double_as_longlong(av), kk);
+                }
+            }
+        }
+        wave_best(a, key);
+        bad = __builtin_amdgcn_ballot_w64(bad) != 0;
+        const bool has = key != ~0ull;
+        const int clw = has ? (int)(key & 0xffffu) : 0;
+        // 2. the owning wave posts the column, then the record
+        if (wv == clw / CPW) {
+            const int b2 = b * kSplitSlices + slice;
+            if (has) {
+                const int cw = clw % CPW;
+                T y0 = T(0), y1 = T(0);
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) {
+                    y0 = (c == cw) ? x[0][c] : y0;
+                    y1 = (c == cw) ? x[1][c] : y1;
+                }
+                if (H == 0) y1 = fma(-mult[pb][64 + lane], prow[pb][clw], y1);
+                T* col = w.xcol + (size_t)b2 * kMaxPanel;
+                col[lane] = y0;
+                col[64 + lane] = y1;
+                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            }
+            if (lane == 0) {
+                const uint64_t pos = has ? (uint64_t)(cpos[clw] & 0xffffff) : 0;
+                const uint64_t id = has ? ((key >> 32) & 0xffffff) : 0;
+                const uint64_t w0 = a | ((uint64_t)((s >> 1) & 1) << 63);
+                const uint64_t w1 = ((uint64_t)((s + 1) & 0x3fff) << 50) |
+                                    (((key >> 31) & 1ull) << 49) |
+                                    ((uint64_t)bad << 48) | (id << 24) | pos;
+                typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+                *reinterpret_cast<u64x2*>(w.xrec + 2 * b2) = u64x2{w0, w1};
+            }
+        }
+        // 4. the other half of step k-1 (rows 64.. while row k is in 0..63)
+        if (H == 0) {
+            const T m = mult[pb][64 + lane];
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+                x[1][c] = fma(-m, prow[pb][wv * CPW + c], x[1][c]);
+        }
+        // 3. wave 0 takes the winner
+        if (wv == 0) {
+            const __amdgpu_buffer_rsrc_t rec =
+                l2_rsrc(w.xrec + 2 * b * kSplitSlices, 16 * kSplitSlices);
+            const uint64_t gbit = (uint64_t)((s >> 1) & 1);
+            const uint64_t tag = (uint64_t)((s + 1) & 0x3fff);
+            uint64_t r0 = 0, r1 = 0;
+            int stw = kStatusOk;
+            long spins = 0;
+            const uint64_t t0 = now_ticks();
+            for (;;) {
+                bool ok = true;
+                if (lane < nslices) {
+                    asm volatile("" ::: "memory");
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rec, lane * 16, 0,
+                                                                         kL2Policy);
+                    r0 = ((uint64_t)(uint32_t)v[1] << 32) | (uint32_t)v[0];
+                    r1 = ((uint64_t)(uint32_t)v[3] << 32) | (uint32_t)v[2];
+                    ok = (r0 >> 63) == gbit && (r1 >> 50) == tag;
+                }
+                if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
+                ++spins;
+                if ((spins & 63) == 0) {
+                    if (now_ticks() - t0 > kWaitTicks) {
+                        stw = kStatusAborted;
+                        break;
+                    }
+                    if (__builtin_amdgcn_readfirstlane(l2_poll(stat, 0)) != kStatusOk) {
+                        stw = kStatusAborted; // another block stopped the panel
+                        break;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (stw == kStatusOk) {
+                const bool in = lane < nslices;
+                uint64_t ga = in ? (r0 & 0x7fffffffffffffffull) : 0ull;
+                uint64_t gk = in ? ((((r1 >> 24) & 0xffffff) << 32) | (uint64_t)lane) : ~0ull;
+                const bool gbad = __builtin_amdgcn_ballot_w64(in && ((r1 >> 48) & 1)) != 0;
+                wave_best(ga, gk);
+                const int ws = (int)(gk & 0xff);
+                const uint64_t wr1 = readlane64(r1, ws);
+                if (gbad)
+                    stw = kStatusNonfinite;
+                else if (ga == 0 || gk == ~0ull)
+                    stw = kStatusSingular;
+                if (stw == kStatusOk) {
+                    const double mag = __longlong_as_double((long long)ga);
+                    const double p = ((wr1 >> 49) & 1) ? -mag : mag;
+                    const int l = (int)(wr1 & 0xffffff);
+                    const T pt = (T)p;
+                    const __amdgpu_buffer_rsrc_t cr = l2_rsrc(
+                        w.xcol + (size_t)(b * kSplitSlices + ws) * kMaxPanel,
+                        sizeof(T) * kMaxPanel);
+                    const T c0 = l2_load<T>(cr, lane), c1 = l2_load<T>(cr, 64 + lane);
+                    const bool in0 = lane > k && lane < nb;
+                    const bool in1 = 64 + lane > k && 64 + lane < nb;
+                    mult[b][lane] = in0 ? c0 / pt : T(0);
+                    mult[b][64 + lane] = in1 ? c1 / pt : T(0);
+                    if (ws == slice) {
+                        // the retiring column's multipliers, at the position
+                        // the column takes (s), for the rows below row k
+                        if (in0) buf_store<T>(c0, prs, lane * row_bytes + (int)sizeof(T) * s, 0);
+                        if (in1)
+                            buf_store<T>(c1, prs, (64 + lane) * row_bytes + (int)sizeof(T) * s,
+                                         0);
+                    }
+                    if (lane == 0) {
+                        pv[k] = p;
+                        pl[k] = l;
+                        if (ws == slice) cstep[clw] = k; // read as ">= k": still active
+                    }
+                    // the exchange: the column at position s moves to l, the
+                    // pivot column to s
+#pragma unroll
+                    for (int q = 0; q < CP / kWave; ++q) {
+                        const int cl = lane + kWave * q;
+                        const int ps = cpos[cl];
+                        cpos[cl] = (ws == slice && cl == clw) ? s : (ps == s ? l : ps);
+                    }
+                }
+            }
+            if (lane == 0) sh_st = stw;
+        }
+        __syncthreads();
+        const int st = sh_st;
+        if (st == kStatusOk) return true;
+        if (slice == 0) { // the steps taken so far, then the failed one
+            for (int t = tid; t < k; t += kSplitThreads) {
+                w.piv_pos[s0 + t] = pl[t];
+                w.piv_val[s0 + t] = pv[t];
+            }
+            if (tid == 0) {
+                w.piv_pos[s] = -1;
+                w.piv_val[s] = 0.0;
+                st_agent(&w.state->bad_step, s);
+                st_agent(&w.state->status, st);
+            }
+        } else if (tid == 0 && st == kStatusAborted) {
+            st_agent(&w.state->status, st);
+        }
+        return false;
+    };
+    const int nb0 = nb < 64 ? nb : 64;
+    for (int k = 0; k < nb0; ++k)
+        if (!step(std::integral_constant<int, 0>{}, k)) return;
+    for (int k = 64; k < nb; ++k)
+        if (!step(std::integral_constant<int, 1>{}, k)) return;
+
+    // the factored rows at the columns' final positions (rows past nb fall
+    // outside the descriptor and are dropped; columns past the panel's
+    // width have cstep -1 and are skipped)
+    const int pos_l = cpos[wv * CPW + c_l];
+    const int soff = r_l * row_bytes + (int)sizeof(T) * (col_ok ? pos_l : s0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = 64 * h + lane;
+        const T p = (T)pv[i < nb ? i : 0];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const T v = h == 0 ? x[0][c] : x[1][c];
+            tw[lane * TBLD + c] = (i < cstep[wv * CPW + c]) ? v / p : v;
+        }
+        __syncthreads();
+        // rows below a retired column's step hold its multipliers already
+        const int cs_l = cstep[wv * CPW + c_l];
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) {
+            const int r = 64 * h + r_l + RS * u;
+            if (r <= cs_l)
+                buf_store<T>(tw[(r_l + RS * u) * TBLD + c_l], prs, soff,
+                             (64 * h + RS * u) * row_bytes);
+        }
+    }
+    for (int t = tid; t < CP; t += kSplitThreads)
+        if (slice * CP + t < width) w.perm[cpos[t]] = cid[t];
+    if (slice == 0)
+        for (int t = tid; t < nb; t += kSplitThreads) {
+            w.piv_pos[s0 + t] = pl[t];
+            w.piv_val[s0 + t] = pv[t];
+        }
+}
+
 // Undo the exchanges of panel steps hi-1 down to lo (step t exchanged
 // positions s0+t and lp[t]) on Q positions per lane at once.  lp0 and lp1
 // hold lp[lane] and lp[lane + 64]; every step's partner is read from them
@@ -1027,6 +1467,44 @@ static bool try_panel_x(int64_t n, int64_t s0, int64_t pend,
     else if (panel_x_fits(width)) launch_panel_x<T, 768, 11>(n, s0, pend, w, stream);
     else return false;
     return true;
+}
+
+template <typename T, int CPW>
+static hipError_t launch_split(int64_t n, int64_t s0, int nb, const BlkWork<T>& w,
+                               hipStream_t stream)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&blk_panel_split<T, CPW>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes<T, CPW>());
+        if (e != hipSuccess) return note_hip_error(e);
+        attr_set = true;
+    }
+    constexpr int CP = kSplitWaves * CPW;
+    const int slices = (int)((n - s0 + CP - 1) / CP);
+    const size_t lds = split_lds_bytes<T, CPW>();
+    hipLaunchKernelGGL((blk_panel_split<T, CPW>), dim3((unsigned)(8 * slices)),
+                       dim3(kSplitThreads), lds, stream, n, s0, nb, slices, w);
+    return hipSuccess;
+}
+
+static bool split_fits(int64_t width)
+{
+    return g_split_on && width <= (int64_t)kSplitSlices * kSplitWaves * 32;
+}
+
+// The column-split panel for a panel of width n - s0 (split_fits).
+template <typename T>
+static hipError_t launch_panel_split(int64_t n, int64_t s0, int nb,
+                                     const BlkWork<T>& w, hipStream_t stream)
+{
+    const int64_t width = n - s0;
+    if (width <= (int64_t)kSplitSlices * kSplitWaves * 8)
+        return launch_split<T, 8>(n, s0, nb, w, stream);
+    if (width <= (int64_t)kSplitSlices * kSplitWaves * 16)
+        return launch_split<T, 16>(n, s0, nb, w, stream);
+    return launch_split<T, 32>(n, s0, nb, w, stream);
 }
 
 template <typename T>
@@ -1135,6 +1613,10 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
     __shared__ int lp[kMaxPanel];
     if (w.state->status != kStatusOk) return;
     const int tid = threadIdx.x;
+    if (tid == 0) { // the next panel's blocks elect an XCD afresh
+        w.claim[0] = 0;
+        w.claim[1] = -1;
+    }
     for (int t = tid; t < kMaxPanel; t += kBlkThreads) {
         const int d = w.moved[t];
         if (d >= 0) {
@@ -1522,10 +2004,17 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     for (int64_t s0 = 0, k = 0; s0 < n; s0 += b, ++k) {
         const int nb = (int)std::min<int64_t>(b, n - s0);
         const int64_t pend = s0 + nb;
-        launch_head<T>(n, s0, w, stream);
+        // the column-split panel needs its blocks resident together, which a
+        // trailing update running beside it (lookahead) could prevent
+        const bool split = !la && split_fits(n - s0);
+        if (!split) launch_head<T>(n, s0, w, stream);
         const int ept = step_ept(n - s0);
-        const bool persistent = ept > 0 && nb > 1;
+        const bool persistent = !split && ept > 0 && nb > 1;
         const ProfMark pm = prof_begin(stream, MC_PROF_PANEL);
+        if (split) {
+            const hipError_t e = launch_panel_split<T>(n, s0, nb, w, stream);
+            if (e != hipSuccess) return e;
+        }
         const bool single_xcd = persistent && try_panel_x<T>(n, s0, pend, w, stream);
         if (persistent && !single_xcd) {
             switch (ept) { // wider than the single-XCD panel: across XCDs
@@ -1537,13 +2026,13 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                 MC_PANEL(1) MC_PANEL(2) MC_PANEL(4) MC_PANEL(8) MC_PANEL(16)
 #undef MC_PANEL
             }
-        } else if (!persistent) {
+        } else if (!persistent && !split) {
             for (int64_t s = s0; s < pend; ++s)
                 launch_step<T>(n, s, s0, pend, w, stream);
         }
         { // the panel's rows read and written once; b^2 w flops
             const double width = (double)(n - s0);
-            prof_end(stream, pm, persistent ? 1 : nb,
+            prof_end(stream, pm, (persistent || split) ? 1 : nb,
                      2.0 * sizeof(T) * nb * width, (double)nb * nb * width);
         }
         if (single_xcd) // unfactored rows; the later steps' exchanges

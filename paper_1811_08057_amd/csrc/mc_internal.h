@@ -56,10 +56,15 @@ struct BlkWork {
     T* dinv;       // inverses of the 16 x 16 diagonal blocks of U11
     int* stepflag; // per panel step: 1 once its pivot row is published
     int* claim;    // single-XCD panel kernel: [0] row-claim counter, [1] elected XCD
+    // column-split panel: per step parity and slice, a 16-byte pivot
+    // candidate record and the candidate's column of the panel rows
+    unsigned long long* xrec; // [2][kSplitSlices][2]
+    T* xcol;                  // [2][kSplitSlices][kMaxPanel]
     DevState* state;
 };
 
 constexpr int64_t kMaxPanel = 128;
+constexpr int kSplitSlices = 32; // compute units of one XCD
 
 size_t blocked_workspace_bytes(int64_t n, int dtype, int64_t b);
 template <typename T>
@@ -69,6 +74,9 @@ template <typename T>
 hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                           int update, BlkWork<T> w, mc_result* out,
                           hipStream_t stream, bool factor, bool lookahead);
+
+// Column-split panel kernel on (default) or off; returns the previous setting.
+int split_panel_set(int on);
 
 size_t plain_workspace_bytes(int64_t n);
 PlainWork plain_carve(void* work, int64_t n);

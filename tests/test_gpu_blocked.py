@@ -188,6 +188,66 @@ def test_lookahead_on_and_off_agree(n, b):
     assert err <= 1e-10 * max(1.0, lu_off.abs().max().item()), err
 
 
+@pytest.mark.parametrize("n,b,dtype", [(2500, 128, torch.float64),
+                                        (5000, 96, torch.float64),
+                                        (5000, 128, torch.float32)])
+def test_split_panel_on_and_off_agree(n, b, dtype):
+    """The column-split panel kernel (the default for panels up to 8192
+    wide; these sizes reach its 16- and 32-column-per-wave forms) and the
+    row-per-block panel kernels both meet the oracle's bar; in FP64 they
+    take the same pivots and give the same factors up to rounding order (in
+    FP32 the two rounding orders may resolve near-ties differently, so
+    only valid permutations are required there)."""
+    a_np = synth.normal(n, 90 + n)
+    a_in = a_np.astype(np.float32).astype(np.float64) if dtype == torch.float32 else a_np
+    ref = O.slogdet(a_in)
+    tol = TOL64 if dtype == torch.float64 else TOL_MIXED
+    a = torch.from_numpy(a_np).to(DEV, dtype)
+    prev = mc.split_panel_enable(True)
+    try:
+        on = run(a_np, b, dtype=dtype)
+        lu_on, perm_on, _ = mc.factor(a, b=b)
+        mc.split_panel_enable(False)
+        off = run(a_np, b, dtype=dtype)
+        lu_off, perm_off, _ = mc.factor(a, b=b)
+    finally:
+        mc.split_panel_enable(prev)
+    assert_parity(on, ref, tol)
+    assert_parity(off, ref, tol)
+    for perm in (perm_on, perm_off):
+        assert torch.equal(torch.sort(perm.long()).values,
+                           torch.arange(n, device=perm.device))
+    if dtype == torch.float32:
+        return  # FP32 rounding differences can reorder near-tied pivots
+    assert torch.equal(perm_on, perm_off)
+    scale = max(1.0, lu_off.abs().max().item())
+    err = (lu_on - lu_off).abs().max().item() / scale
+    print(f"[split] n={n} b={b} {dtype}: max |LU on - LU off| / max|LU| = {err:.3e}")
+    assert err <= 1e-10, err
+
+
+def test_split_panel_singular_wide():
+    """A zero row met inside a panel wider than 4096 (the widest split form)
+    and a zero column: the same info as the oracle with split on and off."""
+    n = 5000
+    a = synth.normal(n, 17)
+    z = a.copy()
+    z[500] = 0.0
+    zc = a.copy()
+    zc[:, 4321] = 0.0
+    for m in (z, zc):
+        ref = O.slogdet(m)
+        prev = mc.split_panel_enable(True)
+        try:
+            on = run(m, 128)
+            mc.split_panel_enable(False)
+            off = run(m, 128)
+        finally:
+            mc.split_panel_enable(prev)
+        assert_parity(on, ref)
+        assert_parity(off, ref)
+
+
 @pytest.mark.parametrize("lookahead", [False, True])
 def test_blocked_graph_replays(lookahead):
     """mc_logdet on the blocked path (with lookahead: side-stream trailing
