@@ -1058,6 +1058,80 @@ __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Largest 32-bit value over the 64 lanes (every lane active), in every
+// lane: the same row shifts and broadcasts as wave_best.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp_max_step(uint32_t x)
+{
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xf, false);
+    return x > o ? x : o;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x)
+{
+    x = dpp_max_step<0x111, 0xf>(x);
+    x = dpp_max_step<0x112, 0xf>(x);
+    x = dpp_max_step<0x114, 0xf>(x);
+    x = dpp_max_step<0x118, 0xf>(x);
+    x = dpp_max_step<0x142, 0xa>(x);
+    x = dpp_max_step<0x143, 0xc>(x);
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// The best (a, k) of the wave (largest a, then smallest k), returned
+// uniformly: the high words of a first, then, only where several lanes
+// share the largest high word, the low words, and only for exact ties the
+// keys.
+__device__ __forceinline__ void wave_best_fast(uint64_t& a, uint64_t& k)
+{
+    const uint32_t hi = (uint32_t)(a >> 32);
+    const uint32_t mhi = wave_max_u32(hi);
+    uint64_t m = __builtin_amdgcn_ballot_w64(hi == mhi);
+    if (__builtin_popcountll(m) > 1) {
+        const bool in = hi == mhi;
+        const uint32_t lo = in ? (uint32_t)a : 0u;
+        const uint32_t mlo = wave_max_u32(lo);
+        m = __builtin_amdgcn_ballot_w64(in && lo == mlo);
+        if (__builtin_popcountll(m) > 1) { // exact ties: the smallest key
+            uint64_t aa = (in && lo == mlo) ? a : 0ull;
+            uint64_t kk = (in && lo == mlo) ? k : ~0ull;
+            wave_best(aa, kk);
+            a = aa;
+            k = kk;
+            return;
+        }
+    }
+    const int l = __builtin_ctzll(m);
+    a = readlane64(a, l);
+    k = readlane64(k, l);
+}
+
+__device__ __forceinline__ double wave_uniform_lane(double v, int l)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float wave_uniform_lane(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 template <typename T, int CPW>
 static size_t split_lds_bytes()
 {
@@ -1073,6 +1147,7 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
     extern __shared__ unsigned char smem_raw[];
     T* tb = reinterpret_cast<T*>(smem_raw); // [wave][64][TBLD] transposes
     __shared__ T prow[2][CP];               // row k of the slice, by step parity
+    __shared__ T nrow[2][CP];               // row k+1 staged during step k
     __shared__ T mult[2][kMaxPanel];        // multipliers c_i / p, by step parity
     __shared__ double pv[kMaxPanel];        // pivot of each step
     __shared__ int pl[kMaxPanel];           // pivot position of each step
@@ -1117,6 +1192,7 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         cstep[t] = ok ? kSplitNone : -1; // active at step k: cstep >= k
         cid[t] = ok ? w.perm[s0 + col] : 0x7fffffff;
         prow[0][t] = prow[1][t] = T(0);
+        nrow[0][t] = nrow[1][t] = T(0);
     }
     for (int t = tid; t < kMaxPanel; t += kSplitThreads) mult[0][t] = mult[1][t] = T(0);
 
@@ -1149,34 +1225,35 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
     }
 
     const __amdgpu_buffer_rsrc_t stat = l2_rsrc(&w.state->status, sizeof(int));
-    // One step (row k in half H of the lanes' rows); false once the panel
-    // stops (a singular or non-finite pivot row, or an aborted wait).
-    auto step = [&](auto hc, int k) -> bool {
-        constexpr int H = decltype(hc)::value;
+    // row 0 for the first step's candidate (no step applied yet)
+    {
+        const int pb0 = (s0 & 1) ^ 1;
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) nrow[pb0][wv * CPW + c] = x[0][c];
+        }
+    }
+    __syncthreads();
+    T keep0 = T(0), keep1 = T(0); // wave 0: the last retiring column's multipliers
+    int keep_s = -1, keep_k = 0;
+    // One step.  B0: step k-1 still reaches rows 0..63; HN: half of row k+1.
+    // Returns false once the panel stops (a singular or non-finite pivot
+    // row, or an aborted wait).
+    auto step = [&](auto b0c, auto hnc, int k) -> bool {
+        constexpr bool B0 = decltype(b0c)::value;
+        constexpr int HN = decltype(hnc)::value;
         const int s = s0 + k, b = s & 1, pb = b ^ 1;
-        // 1. step k-1 on the half holding row k (a retired column is
-        //    updated too: only its rows up to its own step are kept, and
-        //    its multipliers went to W when it retired); the lane holding
-        //    row k posts the row
-        {
-            const T m = mult[pb][64 * H + lane];
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-                x[H][c] = fma(-m, prow[pb][wv * CPW + c], x[H][c]);
-        }
-        if (lane == (k & 63)) {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c) prow[b][wv * CPW + c] = x[H][c];
-        }
-        __syncthreads();
-        // the block's candidate, reduced by every wave alike
+        // 1. row k (the staged row with step k-1 applied here) and the
+        //    block's candidate, reduced by every wave alike
+        const T mk = mult[pb][k];
         uint64_t a = 0, key = ~0ull;
         bool bad = false;
 #pragma unroll
         for (int q = 0; q < CP / kWave; ++q) {
             const int cl = lane + kWave * q;
+            const T v = fma(-mk, prow[pb][cl], nrow[pb][cl]);
+            if (wv == 0) prow[b][cl] = v;
             if (cstep[cl] >= k) { // active (the step retiring it writes k)
-                const T v = prow[b][cl];
                 const double av = fabs((double)v);
                 if (!isfinite(av)) {
                     bad = true;
@@ -1187,22 +1264,27 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                 }
             }
         }
-        wave_best(a, key);
+        wave_best_fast(a, key);
         bad = __builtin_amdgcn_ballot_w64(bad) != 0;
         const bool has = key != ~0ull;
         const int clw = has ? (int)(key & 0xffffu) : 0;
-        // 2. the owning wave posts the column, then the record
+        // 2. the owning wave posts the column (step k-1 applied here), then
+        //    the record
         if (wv == clw / CPW) {
             const int b2 = b * kSplitSlices + slice;
             if (has) {
+                // the column through this wave's (idle) transpose rows: an
+                // LDS address may be dynamic, a register index may not
                 const int cw = clw % CPW;
-                T y0 = T(0), y1 = T(0);
 #pragma unroll
-                for (int c = 0; c < CPW; ++c) {
-                    y0 = (c == cw) ? x[0][c] : y0;
-                    y1 = (c == cw) ? x[1][c] : y1;
-                }
-                if (H == 0) y1 = fma(-mult[pb][64 + lane], prow[pb][clw], y1);
+                for (int c = 0; c < CPW; ++c) tw[lane * TBLD + c] = x[0][c];
+                T y0 = tw[lane * TBLD + cw];
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) tw[lane * TBLD + c] = x[1][c];
+                T y1 = tw[lane * TBLD + cw];
+                const T r = prow[pb][clw];
+                y0 = fma(-mult[pb][lane], r, y0);
+                y1 = fma(-mult[pb][64 + lane], r, y1);
                 T* col = w.xcol + (size_t)b2 * kMaxPanel;
                 col[lane] = y0;
                 col[64 + lane] = y1;
@@ -1219,14 +1301,31 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                 *reinterpret_cast<u64x2*>(w.xrec + 2 * b2) = u64x2{w0, w1};
             }
         }
-        // 4. the other half of step k-1 (rows 64.. while row k is in 0..63)
-        if (H == 0) {
-            const T m = mult[pb][64 + lane];
+        // 3. step k-1 on the registers (a retired column is updated too:
+        //    only its rows up to its own step are kept, and its multipliers
+        //    went to W when it retired)
+        {
+            const T m0 = -mult[pb][lane], m1 = -mult[pb][64 + lane];
 #pragma unroll
-            for (int c = 0; c < CPW; ++c)
-                x[1][c] = fma(-m, prow[pb][wv * CPW + c], x[1][c]);
+            for (int c = 0; c < CPW; ++c) {
+                // the pivot row's entry is the same in every lane: keep it
+                // in scalar registers
+                const T r = wave_uniform(prow[pb][wv * CPW + c]);
+                if (B0) x[0][c] = fma(m0, r, x[0][c]);
+                x[1][c] = fma(m1, r, x[1][c]);
+            }
         }
-        // 3. wave 0 takes the winner
+        // 4. row k+1 (step k-1 now applied) staged for the next step's
+        //    candidate, read from the lane holding it
+        {
+            const int ln = (k + 1) & 63;
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+                const T v = wave_uniform_lane(x[HN][c], ln);
+                if (lane == 0) nrow[b][wv * CPW + c] = v;
+            }
+        }
+        // 5. wave 0 takes the winner
         if (wv == 0) {
             const __amdgpu_buffer_rsrc_t rec =
                 l2_rsrc(w.xrec + 2 * b * kSplitSlices, 16 * kSplitSlices);
@@ -1265,7 +1364,7 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                 uint64_t ga = in ? (r0 & 0x7fffffffffffffffull) : 0ull;
                 uint64_t gk = in ? ((((r1 >> 24) & 0xffffff) << 32) | (uint64_t)lane) : ~0ull;
                 const bool gbad = __builtin_amdgcn_ballot_w64(in && ((r1 >> 48) & 1)) != 0;
-                wave_best(ga, gk);
+                wave_best_fast(ga, gk);
                 const int ws = (int)(gk & 0xff);
                 const uint64_t wr1 = readlane64(r1, ws);
                 if (gbad)
@@ -1285,13 +1384,11 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                     const bool in1 = 64 + lane > k && 64 + lane < nb;
                     mult[b][lane] = in0 ? c0 / pt : T(0);
                     mult[b][64 + lane] = in1 ? c1 / pt : T(0);
-                    if (ws == slice) {
-                        // the retiring column's multipliers, at the position
-                        // the column takes (s), for the rows below row k
-                        if (in0) buf_store<T>(c0, prs, lane * row_bytes + (int)sizeof(T) * s, 0);
-                        if (in1)
-                            buf_store<T>(c1, prs, (64 + lane) * row_bytes + (int)sizeof(T) * s,
-                                         0);
+                    if (ws == slice) { // stored after the barrier
+                        keep0 = in0 ? c0 : T(0);
+                        keep1 = in1 ? c1 : T(0);
+                        keep_s = s;
+                        keep_k = k;
                     }
                     if (lane == 0) {
                         pv[k] = p;
@@ -1312,6 +1409,15 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         }
         __syncthreads();
         const int st = sh_st;
+        if (wv == 0 && keep_s >= 0) {
+            // the retiring column's multipliers, at the position the column
+            // takes (s), for the rows below its step
+            if (lane > keep_k && lane < nb)
+                buf_store<T>(keep0, prs, lane * row_bytes + (int)sizeof(T) * keep_s, 0);
+            if (64 + lane > keep_k && 64 + lane < nb)
+                buf_store<T>(keep1, prs, (64 + lane) * row_bytes + (int)sizeof(T) * keep_s, 0);
+            keep_s = -1;
+        }
         if (st == kStatusOk) return true;
         if (slice == 0) { // the steps taken so far, then the failed one
             for (int t = tid; t < k; t += kSplitThreads) {
@@ -1329,35 +1435,54 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         }
         return false;
     };
-    const int nb0 = nb < 64 ? nb : 64;
-    for (int k = 0; k < nb0; ++k)
-        if (!step(std::integral_constant<int, 0>{}, k)) return;
-    for (int k = 64; k < nb; ++k)
-        if (!step(std::integral_constant<int, 1>{}, k)) return;
+    using B_on = std::true_type;
+    using B_off = std::false_type;
+    using H0 = std::integral_constant<int, 0>;
+    using H1 = std::integral_constant<int, 1>;
+    const int nbA = nb < 63 ? nb : 63;
+    // one exit after the loops: a return from inside them would leave the
+    // data without a use on that path, and the register allocator then
+    // keeps two copies of it alive through every step
+    bool live = true;
+#pragma unroll 1
+    for (int k = 0; k < nbA && live; ++k)
+        live = step(B_on{}, H0{}, k);
+    if (live && nb > 63) live = step(B_on{}, H1{}, 63);
+#pragma unroll 1
+    for (int k = 64; k < nb && live; ++k)
+        live = step(B_off{}, H1{}, k);
+    if (!live) return;
 
     // the factored rows at the columns' final positions (rows past nb fall
     // outside the descriptor and are dropped; columns past the panel's
-    // width have cstep -1 and are skipped)
-    const int pos_l = cpos[wv * CPW + c_l];
-    const int soff = r_l * row_bytes + (int)sizeof(T) * (col_ok ? pos_l : s0);
+    // width have cstep -1 and are skipped).  The lane index goes through an
+    // empty asm so that the addresses below are formed here rather than kept
+    // in registers from the loads across the whole step loop.
+    int lane_f = lane;
+    asm volatile("" : "+v"(lane_f));
+    const int cf_l = lane_f % CPW, rf_l = lane_f / CPW;
+    const int pos_l = cpos[wv * CPW + cf_l];
+    const int soff = rf_l * row_bytes + (int)sizeof(T) * (cbase + cf_l < width ? pos_l : s0);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int i = 64 * h + lane;
+        const int i = 64 * h + lane_f;
         const T p = (T)pv[i < nb ? i : 0];
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
+            if (c % 4 == 0) __builtin_amdgcn_sched_barrier(0); // a few divisions at a time
             const T v = h == 0 ? x[0][c] : x[1][c];
-            tw[lane * TBLD + c] = (i < cstep[wv * CPW + c]) ? v / p : v;
+            tw[lane_f * TBLD + c] = (i < cstep[wv * CPW + c]) ? v / p : v;
         }
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
         // rows below a retired column's step hold its multipliers already
-        const int cs_l = cstep[wv * CPW + c_l];
+        const int cs_l = cstep[wv * CPW + cf_l];
 #pragma unroll
         for (int u = 0; u < CPW; ++u) {
-            const int r = 64 * h + r_l + RS * u;
+            const int r = 64 * h + rf_l + RS * u;
             if (r <= cs_l)
-                buf_store<T>(tw[(r_l + RS * u) * TBLD + c_l], prs, soff,
+                buf_store<T>(tw[(rf_l + RS * u) * TBLD + cf_l], prs, soff,
                              (64 * h + RS * u) * row_bytes);
         }
     }
