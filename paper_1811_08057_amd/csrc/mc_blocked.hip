@@ -1119,19 +1119,6 @@ __device__ __forceinline__ void wave_best_fast(uint64_t& a, uint64_t& k)
     k = readlane64(k, l);
 }
 
-__device__ __forceinline__ double wave_uniform_lane(double v, int l)
-{
-    const uint64_t u = __double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-__device__ __forceinline__ float wave_uniform_lane(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
 template <typename T, int CPW>
 static size_t split_lds_bytes()
 {
@@ -1273,15 +1260,15 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         if (wv == clw / CPW) {
             const int b2 = b * kSplitSlices + slice;
             if (has) {
-                // the column through this wave's (idle) transpose rows: an
-                // LDS address may be dynamic, a register index may not
+                // the column by selects over the wave's columns (a dynamic
+                // register index would move the data to scratch memory)
                 const int cw = clw % CPW;
+                T y0 = T(0), y1 = T(0);
 #pragma unroll
-                for (int c = 0; c < CPW; ++c) tw[lane * TBLD + c] = x[0][c];
-                T y0 = tw[lane * TBLD + cw];
-#pragma unroll
-                for (int c = 0; c < CPW; ++c) tw[lane * TBLD + c] = x[1][c];
-                T y1 = tw[lane * TBLD + cw];
+                for (int c = 0; c < CPW; ++c) {
+                    y0 = (c == cw) ? x[0][c] : y0;
+                    y1 = (c == cw) ? x[1][c] : y1;
+                }
                 const T r = prow[pb][clw];
                 y0 = fma(-mult[pb][lane], r, y0);
                 y1 = fma(-mult[pb][64 + lane], r, y1);
@@ -1314,16 +1301,20 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                 if (B0) x[0][c] = fma(m0, r, x[0][c]);
                 x[1][c] = fma(m1, r, x[1][c]);
             }
-        }
-        // 4. row k+1 (step k-1 now applied) staged for the next step's
-        //    candidate, read from the lane holding it
-        {
-            const int ln = (k + 1) & 63;
+            // a use of the updated data here, so that the update stays
+            // before the barrier below rather than being moved onto the
+            // next step's critical path
 #pragma unroll
             for (int c = 0; c < CPW; ++c) {
-                const T v = wave_uniform_lane(x[HN][c], ln);
-                if (lane == 0) nrow[b][wv * CPW + c] = v;
+                if (B0) asm volatile("" ::"v"(x[0][c]));
+                asm volatile("" ::"v"(x[1][c]));
             }
+        }
+        // 4. row k+1 (step k-1 now applied) staged for the next step's
+        //    candidate by the lane holding it
+        if (lane == ((k + 1) & 63)) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) nrow[b][wv * CPW + c] = x[HN][c];
         }
         // 5. wave 0 takes the winner
         if (wv == 0) {
