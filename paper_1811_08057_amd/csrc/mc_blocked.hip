@@ -1139,6 +1139,7 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
     __shared__ double pv[kMaxPanel];        // pivot of each step
     __shared__ int pl[kMaxPanel];           // pivot position of each step
     __shared__ int cpos[CP], cstep[CP], cid[CP];
+    __shared__ int invpos[kMaxPanel]; // panel position s0+t: its column here, or -1
     __shared__ int sh_slice, sh_st, sh_ws, sh_cl;
 
     const int n = (int)n64, s0 = (int)s064, width = n - s0;
@@ -1181,7 +1182,11 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         prow[0][t] = prow[1][t] = T(0);
         nrow[0][t] = nrow[1][t] = T(0);
     }
-    for (int t = tid; t < kMaxPanel; t += kSplitThreads) mult[0][t] = mult[1][t] = T(0);
+    for (int t = tid; t < kMaxPanel; t += kSplitThreads) {
+        mult[0][t] = mult[1][t] = T(0);
+        const int cl = t - slice * CP; // position s0+t holds column t at the start
+        invpos[t] = (cl >= 0 && cl < CP && t < width) ? cl : -1;
+    }
 
     // the slice's rows, loaded coalesced and transposed through LDS.  One
     // buffer descriptor covers the panel rows (rows past nb read as zero);
@@ -1221,6 +1226,14 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         }
     }
     __syncthreads();
+    // the scan's columns lane + 64 q: their ids, and which are still active
+    int cidr[CP / kWave];
+    uint32_t act = 0;
+#pragma unroll
+    for (int q = 0; q < CP / kWave; ++q) {
+        cidr[q] = cid[lane + kWave * q];
+        if (cstep[lane + kWave * q] == kSplitNone) act |= 1u << q;
+    }
     T keep0 = T(0), keep1 = T(0); // wave 0: the last retiring column's multipliers
     int keep_s = -1, keep_k = 0;
     // One step.  B0: step k-1 still reaches rows 0..63; HN: half of row k+1.
@@ -1240,12 +1253,12 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
             const int cl = lane + kWave * q;
             const T v = fma(-mk, prow[pb][cl], nrow[pb][cl]);
             if (wv == 0) prow[b][cl] = v;
-            if (cstep[cl] >= k) { // active (the step retiring it writes k)
+            if ((act >> q) & 1u) {
                 const double av = fabs((double)v);
                 if (!isfinite(av)) {
                     bad = true;
                 } else {
-                    const uint64_t kk = ((uint64_t)(uint32_t)cid[cl] << 32) |
+                    const uint64_t kk = ((uint64_t)(uint32_t)cidr[q] << 32) |
                                         ((uint64_t)(v < T(0)) << 31) | (uint64_t)cl;
                     split_take(a, key, (uint64_t)__double_as_longlong(av), kk);
                 }
@@ -1263,10 +1276,10 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                 // the column by selects over the wave's columns (a dynamic
                 // register index would move the data to scratch memory)
                 const int cw = clw % CPW;
-                T y0 = T(0), y1 = T(0);
+                T y0 = T(0), y1 = T(0); // rows 0..63 matter only while k < 63
 #pragma unroll
                 for (int c = 0; c < CPW; ++c) {
-                    y0 = (c == cw) ? x[0][c] : y0;
+                    if (B0) y0 = (c == cw) ? x[0][c] : y0;
                     y1 = (c == cw) ? x[1][c] : y1;
                 }
                 const T r = prow[pb][clw];
@@ -1384,15 +1397,19 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                     if (lane == 0) {
                         pv[k] = p;
                         pl[k] = l;
-                        if (ws == slice) cstep[clw] = k; // read as ">= k": still active
-                    }
-                    // the exchange: the column at position s moves to l, the
-                    // pivot column to s
-#pragma unroll
-                    for (int q = 0; q < CP / kWave; ++q) {
-                        const int cl = lane + kWave * q;
-                        const int ps = cpos[cl];
-                        cpos[cl] = (ws == slice && cl == clw) ? s : (ps == s ? l : ps);
+                        if (ws == slice) cstep[clw] = k;
+                        sh_ws = ws;
+                        sh_cl = clw;
+                        // the exchange: the column at position s moves to l,
+                        // the pivot column to s (positions past the panel
+                        // are never looked up, so only theirs is not kept)
+                        if (l != s) {
+                            const int jt = invpos[k]; // the column at s, if here
+                            if (ws == slice) cpos[clw] = s;
+                            if (jt >= 0) cpos[jt] = l;
+                            invpos[k] = (ws == slice) ? clw : -1;
+                            if (l - s0 < nb) invpos[l - s0] = jt;
+                        }
                     }
                 }
             }
@@ -1400,6 +1417,8 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         }
         __syncthreads();
         const int st = sh_st;
+        if (st == kStatusOk && sh_ws == slice && lane == (sh_cl & 63))
+            act &= ~(1u << (sh_cl >> 6)); // the column this step retired
         if (wv == 0 && keep_s >= 0) {
             // the retiring column's multipliers, at the position the column
             // takes (s), for the rows below its step
