@@ -1383,17 +1383,10 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                     const __amdgpu_buffer_rsrc_t cr = l2_rsrc(
                         w.xcol + (size_t)(b * kSplitSlices + ws) * kMaxPanel,
                         sizeof(T) * kMaxPanel);
+                    // the column's loads first; the reciprocal of the pivot
+                    // and the bookkeeping below overlap them
                     const T c0 = l2_load<T>(cr, lane), c1 = l2_load<T>(cr, 64 + lane);
-                    const bool in0 = lane > k && lane < nb;
-                    const bool in1 = 64 + lane > k && 64 + lane < nb;
-                    mult[b][lane] = in0 ? c0 / pt : T(0);
-                    mult[b][64 + lane] = in1 ? c1 / pt : T(0);
-                    if (ws == slice) { // stored after the barrier
-                        keep0 = in0 ? c0 : T(0);
-                        keep1 = in1 ? c1 : T(0);
-                        keep_s = s;
-                        keep_k = k;
-                    }
+                    const T rp = T(1) / pt;
                     if (lane == 0) {
                         pv[k] = p;
                         pl[k] = l;
@@ -1410,6 +1403,16 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                             invpos[k] = (ws == slice) ? clw : -1;
                             if (l - s0 < nb) invpos[l - s0] = jt;
                         }
+                    }
+                    const bool in0 = lane > k && lane < nb;
+                    const bool in1 = 64 + lane > k && 64 + lane < nb;
+                    mult[b][lane] = in0 ? c0 * rp : T(0);
+                    mult[b][64 + lane] = in1 ? c1 * rp : T(0);
+                    if (ws == slice) { // stored after the barrier
+                        keep0 = in0 ? c0 : T(0);
+                        keep1 = in1 ? c1 : T(0);
+                        keep_s = s;
+                        keep_k = k;
                     }
                 }
             }
