@@ -44,8 +44,9 @@ KERNEL_SOURCE = {
     "plain_step": "paper_1811_08057_amd/csrc/mc_plain.hip",
 }
 KERNEL_NAME = {
-    "panel": ("panel chain: blk_panel_x (one XCD; blk_panel across XCDs for "
-              "panels wider than 8448 columns)"),
+    "panel": ("panel chain: blk_panel_split (one XCD, column slices; the "
+              "row-per-block blk_panel_x / blk_panel for panels wider than "
+              "8192 columns or with lookahead)"),
     "update": "gemm_scalar (trailing update, FP64 MFMA)",
     "update_f32": "gemm_scalar (trailing update, FP32 MFMA)",
     "update_bf16x3": "gemm_bf16x3 (trailing update, split-BF16x3 MFMA)",
