@@ -936,6 +936,24 @@ blk_panel_x(int64_t n64, int64_t s064, int64_t pend64, int nslots, BlkWork<T> w)
     }
 }
 
+// Undo the exchanges of panel steps hi-1 down to lo (step t exchanged
+// positions s0+t and lp[t]) on Q positions per lane at once.  lp0 and lp1
+// hold lp[lane] and lp[lane + 64]; every step's partner is read from them
+// with readlane (lo, hi and the step index are wave-uniform).
+template <int Q>
+__device__ __forceinline__ void undo_exchanges(int (&pos)[Q], int s0, int lo,
+                                               int hi, int lp0, int lp1)
+{
+    for (int t = hi - 1; t >= lo; --t) {
+        const int b = t < kWave ? __builtin_amdgcn_readlane(lp0, t)
+                                : __builtin_amdgcn_readlane(lp1, t - kWave);
+        const int a = s0 + t;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            pos[q] = pos[q] == a ? b : (pos[q] == b ? a : pos[q]);
+    }
+}
+
 // ---- column-split panel (one XCD) ----
 //
 // For panels at most kSplitSlices * 256 positions wide.  P blocks on one
@@ -1182,6 +1200,19 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
         prow[0][t] = prow[1][t] = T(0);
         nrow[0][t] = nrow[1][t] = T(0);
     }
+    if (slice == 0) {
+        // this map set's entries from two panels back return to the
+        // identity; the stores complete before the first barrier, so before
+        // any record of this block, so before any block's final map entries
+        for (int t = tid; t < kMaxPanel; t += kSplitThreads) {
+            const int d = w.moved[t];
+            if (d >= 0) {
+                w.colsrc[d] = d;
+                w.moved[t] = -1;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    }
     for (int t = tid; t < kMaxPanel; t += kSplitThreads) {
         mult[0][t] = mult[1][t] = T(0);
         const int cl = t - slice * CP; // position s0+t holds column t at the start
@@ -1390,7 +1421,10 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
                     if (lane == 0) {
                         pv[k] = p;
                         pl[k] = l;
-                        if (ws == slice) cstep[clw] = k;
+                        if (ws == slice) {
+                            cstep[clw] = k;
+                            w.srcp[k] = s0 + slice * CP + clw; // where it started
+                        }
                         sh_ws = ws;
                         sh_cl = clw;
                         // the exchange: the column at position s moves to l,
@@ -1501,30 +1535,22 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
     }
     for (int t = tid; t < CP; t += kSplitThreads)
         if (slice * CP + t < width) w.perm[cpos[t]] = cid[t];
+    // the column maps of the panel's exchanges for the rows below it (w
+    // carries this panel's set): a trailing position d >= pend that a step
+    // exchanged reads from where its final column started (srcp, the panel
+    // columns' sources, went out as the steps were taken)
+    for (int t = tid; t < CP; t += kSplitThreads) {
+        const int col = slice * CP + t, d = cpos[t];
+        if (col < width && d >= s0 + nb && d != s0 + col) w.colsrc[d] = s0 + col;
+    }
     if (slice == 0)
         for (int t = tid; t < nb; t += kSplitThreads) {
             w.piv_pos[s0 + t] = pl[t];
             w.piv_val[s0 + t] = pv[t];
+            if (pl[t] >= s0 + nb) w.moved[t] = pl[t];
         }
 }
 
-// Undo the exchanges of panel steps hi-1 down to lo (step t exchanged
-// positions s0+t and lp[t]) on Q positions per lane at once.  lp0 and lp1
-// hold lp[lane] and lp[lane + 64]; every step's partner is read from them
-// with readlane (lo, hi and the step index are wave-uniform).
-template <int Q>
-__device__ __forceinline__ void undo_exchanges(int (&pos)[Q], int s0, int lo,
-                                               int hi, int lp0, int lp1)
-{
-    for (int t = hi - 1; t >= lo; --t) {
-        const int b = t < kWave ? __builtin_amdgcn_readlane(lp0, t)
-                                : __builtin_amdgcn_readlane(lp1, t - kWave);
-        const int a = s0 + t;
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-            pos[q] = pos[q] == a ? b : (pos[q] == b ? a : pos[q]);
-    }
-}
 
 // Panel rows published before the last steps: apply the exchanges of the
 // steps after their own (one wavefront per row; sources found by undoing
@@ -1822,7 +1848,7 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
 //     X_J = R_J * inv(U11[J, J])                     (MFMA)
 // with A21[i][t] = W[i][srcp[t]] (the exchanges folded into the load).  X is
 // kept per wavefront in LDS; rows past n and columns past nb are zeros.
-template <typename T>
+template <typename T, bool INV>
 __global__ void __launch_bounds__(kBlkThreads)
 blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
 {
@@ -1850,6 +1876,10 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
     T* Ub = reinterpret_cast<T*>(smem_raw) + kTrsmRows * xld;
     T* Dv = Ub + ntri * 256;
     for (int t = tid; t < nb; t += kBlkThreads) src_sh[t] = w.srcp[t];
+    if (INV && blockIdx.x == 0 && tid == 0) { // after a column-split panel:
+        w.claim[0] = 0;                       // the next panel's blocks
+        w.claim[1] = -1;                      // elect an XCD afresh
+    }
     {
         const int er = tid >> 4, ec = tid & 15;
         T st[kMaxTri + kMaxBlk];
@@ -1862,8 +1892,14 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
                 st[bi] = (J < nblk && t < nb) ? U[(int64_t)(16 * K + er) * ldw + t] : T(0);
             }
 #pragma unroll
-        for (int J = 0; J < kMaxBlk; ++J)
-            st[kMaxTri + J] = J < nblk ? w.dinv[J * 256 + tid] : T(0);
+        for (int J = 0; J < kMaxBlk; ++J) {
+            // the inverted diagonal blocks, or (INV) the blocks themselves
+            const int t = 16 * J + ec;
+            if (INV)
+                st[kMaxTri + J] = (J < nblk && t < nb) ? U[(int64_t)(16 * J + er) * ldw + t] : T(0);
+            else
+                st[kMaxTri + J] = J < nblk ? w.dinv[J * 256 + tid] : T(0);
+        }
         bi = 0;
 #pragma unroll
         for (int J = 1; J < kMaxBlk; ++J)
@@ -1872,7 +1908,12 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
                 if (J < nblk) Ub[bi * 256 + tid] = st[bi];
 #pragma unroll
         for (int J = 0; J < kMaxBlk; ++J)
-            if (J < nblk) Dv[J * 256 + tid] = st[kMaxTri + J];
+            if (J < nblk) {
+                if (INV) // the blocks go to the (still unused) solve rows
+                    reinterpret_cast<T*>(smem_raw)[J * 272 + er * 17 + ec] = st[kMaxTri + J];
+                else
+                    Dv[J * 256 + tid] = st[kMaxTri + J];
+            }
     }
     __syncthreads();
     // every gathered entry of A21 first (one memory latency for all blocks)
@@ -1885,6 +1926,32 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
             const int64_t row = i0 + P::drow(lane, r);
             g[J][r] = (J < nblk && row < n && t < nb) ? W[row * ldw + src_sh[t]] : T(0);
         }
+    }
+    if (INV) {
+        // the diagonal blocks' inverses (unit upper triangular: column c of
+        // block J solves U_JJ x = e_c by back substitution), while the
+        // gathers above are in flight
+        const T* Ud = reinterpret_cast<const T*>(smem_raw);
+        if (tid < nblk * 16) {
+            const int J = tid >> 4, c = tid & 15;
+            T x[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) x[r] = (r == c) ? T(1) : T(0);
+#pragma unroll
+            for (int r = 14; r >= 0; --r) {
+                if (r >= c) continue;
+                T sum = 0;
+#pragma unroll
+                for (int v = r + 1; v < 16; ++v) {
+                    if (v > c) break;
+                    sum = fma(Ud[J * 272 + r * 17 + v], x[v], sum);
+                }
+                x[r] = -sum;
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) Dv[(J * 16 + r) * 16 + c] = x[r];
+        }
+        __syncthreads(); // the inverses are in, the solve rows free again
     }
 #pragma unroll
     for (int J = 0; J < kMaxPanel / 16; ++J) {
@@ -2127,11 +2194,13 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
 {
     static bool attr_set = false;
     if (!attr_set && trsm_mfma_lds_bytes<T>((int)kMaxPanel) > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&blk_trsm_mfma<T>),
-            hipFuncAttributeMaxDynamicSharedMemorySize,
-            (int)trsm_mfma_lds_bytes<T>((int)kMaxPanel));
-        if (e != hipSuccess) return note_hip_error(e);
+        for (const void* f : {reinterpret_cast<const void*>(&blk_trsm_mfma<T, false>),
+                              reinterpret_cast<const void*>(&blk_trsm_mfma<T, true>)}) {
+            const hipError_t e = hipFuncSetAttribute(
+                f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                (int)trsm_mfma_lds_bytes<T>((int)kMaxPanel));
+            if (e != hipSuccess) return note_hip_error(e);
+        }
         attr_set = true;
     }
     hipLaunchKernelGGL(blk_init<T>, dim3((unsigned)n), dim3(kBlkThreads), 0,
@@ -2149,8 +2218,8 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         const int ept = step_ept(n - s0);
         const bool persistent = !split && ept > 0 && nb > 1;
         const ProfMark pm = prof_begin(stream, MC_PROF_PANEL);
-        if (split) {
-            const hipError_t e = launch_panel_split<T>(n, s0, nb, w, stream);
+        if (split) { // the panel's column maps are written by the kernel
+            const hipError_t e = launch_panel_split<T>(n, s0, nb, panel_view(w, k), stream);
             if (e != hipSuccess) return e;
         }
         const bool single_xcd = persistent && try_panel_x<T>(n, s0, pend, w, stream);
@@ -2182,17 +2251,24 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         if (pend >= n) break;
         const int64_t rows = n - pend;
         const BlkWork<T> wk = panel_view(w, k);
-        hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
-                           s0, nb, wk);
+        if (!split) // (the column-split kernel did this work itself)
+            hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
+                               s0, nb, wk);
         if (pending) { // the previous panel's update of the rows below
             const hipError_t e = hipStreamWaitEvent(stream, la->join, 0);
             if (e != hipSuccess) return note_hip_error(e);
             pending = false;
         }
-        hipLaunchKernelGGL(blk_trsm_mfma<T>,
-                           dim3((unsigned)((rows + kTrsmRows - 1) / kTrsmRows)),
-                           dim3(kBlkThreads), trsm_mfma_lds_bytes<T>(nb), stream,
-                           n, s0, nb, wk);
+        {
+            const dim3 grid((unsigned)((rows + kTrsmRows - 1) / kTrsmRows));
+            const size_t lds = trsm_mfma_lds_bytes<T>(nb);
+            if (split) // inverts U11's diagonal blocks itself
+                hipLaunchKernelGGL((blk_trsm_mfma<T, true>), grid, dim3(kBlkThreads), lds,
+                                   stream, n, s0, nb, wk);
+            else
+                hipLaunchKernelGGL((blk_trsm_mfma<T, false>), grid, dim3(kBlkThreads), lds,
+                                   stream, n, s0, nb, wk);
+        }
         // with a side stream: the next panel's rows first, on the caller's
         // stream, the rest beside the next panel; else one launch for all
         const int64_t next = la ? std::min<int64_t>(b, rows) : rows;
