@@ -1823,19 +1823,14 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
     __syncthreads();
     for (int e = tid; e < nblk * 16; e += kBlkThreads) {
         const int J = e >> 4, c = e & 15;
-        T x[16];
+        T x[16]; // column form, as in the solve's own inverses
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = (r == c) ? T(1) : T(0);
 #pragma unroll
-        for (int r = 14; r >= 0; --r) {
-            if (r >= c) continue;
-            T sum = 0;
+        for (int v = 15; v >= 1; --v) {
+            if (v > c) continue;
 #pragma unroll
-            for (int v = r + 1; v < 16; ++v) {
-                if (v > c) break;
-                sum = fma(Ud[J][r][v], x[v], sum);
-            }
-            x[r] = -sum;
+            for (int r = 0; r < v; ++r) x[r] = fma(-Ud[J][r][v], x[v], x[r]);
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) w.dinv[(J * 16 + r) * 16 + c] = x[r];
@@ -1934,19 +1929,16 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
         const T* Ud = reinterpret_cast<const T*>(smem_raw);
         if (tid < nblk * 16) {
             const int J = tid >> 4, c = tid & 15;
+            // column form: once x[v] is final, every row above takes its
+            // share at once (a dependency chain of 15 FMAs, not ~120)
             T x[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) x[r] = (r == c) ? T(1) : T(0);
 #pragma unroll
-            for (int r = 14; r >= 0; --r) {
-                if (r >= c) continue;
-                T sum = 0;
+            for (int v = 15; v >= 1; --v) {
+                if (v > c) continue; // x[v] = 0 there
 #pragma unroll
-                for (int v = r + 1; v < 16; ++v) {
-                    if (v > c) break;
-                    sum = fma(Ud[J * 272 + r * 17 + v], x[v], sum);
-                }
-                x[r] = -sum;
+                for (int r = 0; r < v; ++r) x[r] = fma(-Ud[J * 272 + r * 17 + v], x[v], x[r]);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) Dv[(J * 16 + r) * 16 + c] = x[r];
