@@ -1837,6 +1837,15 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
     }
 }
 
+// Order a wavefront's LDS accesses around this point for the compiler (no
+// instruction: the hardware already completes them in order).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // L21 = A21 * U11^{-1} on the matrix cores, one wavefront per 16 rows, in
 // 16-column blocks J (forward substitution by blocks):
 //     R_J = A21[:, J] - sum_{K<J} X_K U11[K, J]      (MFMA, K = 16 per block)
@@ -1960,9 +1969,12 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
                 acc = P::mma(a, b, acc);
             }
         }
+        // X is this wavefront's own (the other LDS data is read-only here):
+        // a wavefront's LDS accesses complete in order, so ordering them for
+        // the compiler is all the synchronisation needed
 #pragma unroll
         for (int r = 0; r < 4; ++r) X[P::drow(lane, r) * xld + 16 * J + cin] = acc[r];
-        __syncthreads();
+        wave_lds_sync();
         typename P::Acc x = {0, 0, 0, 0};
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) {
@@ -1970,10 +1982,10 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
             const T b = Dv[(J * 16 + 4 * kq + kl) * 16 + cin];
             x = P::mma(a, b, x);
         }
-        __syncthreads();
+        wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < 4; ++r) X[P::drow(lane, r) * xld + 16 * J + cin] = x[r];
-        __syncthreads();
+        wave_lds_sync();
     }
     for (int e = lane; e < 16 * nb; e += kWave) {
         const int ii = e / nb, tt = e - ii * nb;
