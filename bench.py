@@ -46,8 +46,9 @@ KERNEL_SOURCE = {
 KERNEL_NAME = {
     "panel": ("panel chain: blk_panel_split (one XCD, column slices; the "
               "row-per-block blk_panel_x / blk_panel for panels wider than "
-              "8192 columns or with lookahead)"),
-    "update": "gemm_scalar (trailing update, FP64 MFMA)",
+              "8192 columns)"),
+    "update": ("gemm_scalar (trailing update, FP64 MFMA; beside a panel, "
+               "gemm_scalar_spare on the XCDs the panel leaves free)"),
     "update_f32": "gemm_scalar (trailing update, FP32 MFMA)",
     "update_bf16x3": "gemm_bf16x3 (trailing update, split-BF16x3 MFMA)",
     "plain_step": "plain_step (unblocked condensation step)",
@@ -69,9 +70,10 @@ def parse():
     p.add_argument("--no-plain", action="store_true",
                    help="skip timing the plain FP64 GPU path beside it")
     p.add_argument("--plain-steps", type=int, default=2)
-    p.add_argument("--lookahead", default="off", choices=["on", "off"],
-                   help="blocked path: split trailing updates over two "
-                        "streams (on) or keep one stream (off)")
+    p.add_argument("--lookahead", default="on", choices=["on", "off"],
+                   help="blocked path: run each trailing update beside the "
+                        "next panel on a second stream (on) or keep one "
+                        "stream (off)")
     p.add_argument("--profile-steps", type=int, default=3,
                    help="steps of the separate kernel-timing pass")
     p.add_argument("--no-cpu", action="store_true")

@@ -216,8 +216,10 @@ def default_panel(n: int, dtype=torch.float64) -> int:
 
 
 def lookahead_enable(on: bool = True) -> bool:
-    """Split each blocked trailing update across two streams, or keep every
-    kernel on the caller's stream (the default); returns the previous
+    """Lookahead on the blocked path (the default): beside each
+    column-split panel, the previous panel's trailing update beyond that
+    panel's rows runs on a second stream, on the XCDs the panel leaves free.
+    Off keeps every kernel on the caller's stream.  Returns the previous
     setting."""
     return bool(lib().mc_lookahead_enable(1 if on else 0))
 

@@ -67,6 +67,7 @@ blk_init(const T* __restrict__ A, int64_t lda, int64_t n, BlkWork<T> w)
             w.state->bad_step = 0;
             w.claim[0] = 0;
             w.claim[1] = -1;
+            w.claim[2] = 0;
         }
     }
 }
@@ -541,13 +542,6 @@ blk_panel(int64_t n, int64_t s0, int64_t pend, BlkWork<T> w)
 // one row read, the pivot search and the publication.  All slots must be
 // resident together (S <= 32, one block per compute unit of the XCD); every
 // wait is bounded.
-
-__device__ __forceinline__ int xcc_id()
-{
-    int x;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
-    return x & 0xf;
-}
 
 // L2-served loads (sc0 nt) through a buffer descriptor covering `bytes`
 // from base (out-of-range offsets read as zero).
@@ -1145,7 +1139,7 @@ static size_t split_lds_bytes()
 
 template <typename T, int CPW>
 __global__ void __launch_bounds__(kSplitThreads)
-blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
+blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, BlkWork<T> w)
 {
     constexpr int CP = kSplitWaves * CPW; // columns per slice
     constexpr int TBLD = CPW + 1;
@@ -1164,12 +1158,15 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, BlkWork<T> w)
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (tid == 0) {
-        // block 0 publishes its XCD; blocks elsewhere leave, the others
-        // take slices from a counter in that XCD's L2
+        // block 0 publishes its XCD (or, beside a trailing update that
+        // leaves it alone, the XCD is 0); blocks elsewhere leave, the
+        // others take slices from a counter in that XCD's L2
         const int x = xcc_id();
         int e = x;
         if (w.state->status != kStatusOk) {
             e = -1;
+        } else if (on_xcc0) {
+            e = 0;
         } else if (blockIdx.x == 0) {
             st_agent(&w.claim[1], x);
         } else {
@@ -1635,7 +1632,7 @@ static bool try_panel_x(int64_t n, int64_t s0, int64_t pend,
 
 template <typename T, int CPW>
 static hipError_t launch_split(int64_t n, int64_t s0, int nb, const BlkWork<T>& w,
-                               hipStream_t stream)
+                               hipStream_t stream, bool on_xcc0)
 {
     static bool attr_set = false;
     if (!attr_set) {
@@ -1649,7 +1646,8 @@ static hipError_t launch_split(int64_t n, int64_t s0, int nb, const BlkWork<T>& 
     const int slices = (int)((n - s0 + CP - 1) / CP);
     const size_t lds = split_lds_bytes<T, CPW>();
     hipLaunchKernelGGL((blk_panel_split<T, CPW>), dim3((unsigned)(8 * slices)),
-                       dim3(kSplitThreads), lds, stream, n, s0, nb, slices, w);
+                       dim3(kSplitThreads), lds, stream, n, s0, nb, slices,
+                       on_xcc0 ? 1 : 0, w);
     return hipSuccess;
 }
 
@@ -1658,17 +1656,24 @@ static bool split_fits(int64_t width)
     return g_split_on && width <= (int64_t)kSplitSlices * kSplitWaves * 32;
 }
 
-// The column-split panel for a panel of width n - s0 (split_fits).
+// The column-split panel for a panel of width n - s0 (split_fits): the
+// fewest columns per wave that keep the slices within 32.  Beside a
+// trailing update (on_xcc0: the update leaves XCD 0 to the panel) at most
+// 31 where the width allows, so that one compute unit there stays free for
+// that update's blocks that land on it and leave: with every unit held,
+// its blocks on the other XCDs would wait on them (workgroups are
+// dispatched in order).
 template <typename T>
 static hipError_t launch_panel_split(int64_t n, int64_t s0, int nb,
-                                     const BlkWork<T>& w, hipStream_t stream)
+                                     const BlkWork<T>& w, hipStream_t stream,
+                                     bool on_xcc0)
 {
-    const int64_t width = n - s0;
-    if (width <= (int64_t)kSplitSlices * kSplitWaves * 8)
-        return launch_split<T, 8>(n, s0, nb, w, stream);
-    if (width <= (int64_t)kSplitSlices * kSplitWaves * 16)
-        return launch_split<T, 16>(n, s0, nb, w, stream);
-    return launch_split<T, 32>(n, s0, nb, w, stream);
+    const int64_t width = n - s0, slices = on_xcc0 ? kSplitSlices - 1 : kSplitSlices;
+    if (width <= slices * kSplitWaves * 8)
+        return launch_split<T, 8>(n, s0, nb, w, stream, on_xcc0);
+    if (width <= slices * kSplitWaves * 16)
+        return launch_split<T, 16>(n, s0, nb, w, stream, on_xcc0);
+    return launch_split<T, 32>(n, s0, nb, w, stream, on_xcc0);
 }
 
 template <typename T>
@@ -1777,9 +1782,10 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
     __shared__ int lp[kMaxPanel];
     if (w.state->status != kStatusOk) return;
     const int tid = threadIdx.x;
-    if (tid == 0) { // the next panel's blocks elect an XCD afresh
-        w.claim[0] = 0;
+    if (tid == 0) { // the next panel's blocks elect an XCD afresh; the
+        w.claim[0] = 0; // trailing update's tile counter starts at zero
         w.claim[1] = -1;
+        w.claim[2] = 0;
     }
     for (int t = tid; t < kMaxPanel; t += kBlkThreads) {
         const int d = w.moved[t];
@@ -1882,7 +1888,8 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
     for (int t = tid; t < nb; t += kBlkThreads) src_sh[t] = w.srcp[t];
     if (INV && blockIdx.x == 0 && tid == 0) { // after a column-split panel:
         w.claim[0] = 0;                       // the next panel's blocks
-        w.claim[1] = -1;                      // elect an XCD afresh
+        w.claim[1] = -1;                      // elect an XCD afresh; the
+        w.claim[2] = 0;                       // update's tile counter
     }
     {
         const int er = tid >> 4, ec = tid & 15;
@@ -2116,14 +2123,17 @@ static size_t trsm_mfma_lds_bytes(int nb)
 // The next panel only needs its own rows brought up to date, so the
 // trailing update is split: the next panel's rows on the caller's stream,
 // the rest on a second stream, where it runs beside the next panel's
-// factorisation (whose chain occupies one XCD).  Fork and join are events;
-// the caller's stream waits for the join before the next triangular solve
-// and before returning.  One side stream and event pair per device, reused
+// factorisation.  That panel's chain holds XCD 0 (a column-split panel
+// elects it when told to) and the update leaves XCD 0 alone, so neither
+// waits for the other's compute units.  Fork and join are events; the
+// caller's stream waits for the join before the next triangular solve and
+// before returning.  One side stream and event pair per device, reused
 // under a lock held while a call enqueues its work.
 struct Lookahead {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     bool ready = false, failed = false;
+    bool all_xccs = false; // the device exposes its eight XCDs (ids 0..7)
 };
 
 constexpr int kMaxDevices = 64;
@@ -2145,6 +2155,10 @@ static Lookahead* lookahead_get()
             (void)hipGetLastError();
             return nullptr;
         }
+        int xccs = 0;
+        la.all_xccs = hipDeviceGetAttribute(&xccs, hipDeviceAttributeNumberOfXccs, dev) ==
+                          hipSuccess && xccs == 8;
+        (void)hipGetLastError();
         la.ready = true;
     }
     return la.ready ? &la : nullptr;
@@ -2165,7 +2179,8 @@ static BlkWork<T> panel_view(const BlkWork<T>& w, int64_t k)
 
 template <typename T>
 static hipError_t trailing(const BlkWork<T>& w, int update, int64_t s0, int nb,
-                           int64_t r0, int64_t m, int64_t n, hipStream_t st)
+                           int64_t r0, int64_t m, int64_t n, hipStream_t st,
+                           unsigned int* tile_ctr)
 {
     const int64_t pend = s0 + nb;
     GemmArgs<T> g;
@@ -2182,6 +2197,7 @@ static hipError_t trailing(const BlkWork<T>& w, int update, int64_t s0, int nb,
     g.ldu = w.ldw;
     g.colsrc = w.colsrc;
     g.state = w.state;
+    g.tile_ctr = tile_ctr;
     const ProfMark pm = prof_begin(st);
     const hipError_t e = launch_trailing_update(g, update, st);
     if (e != hipSuccess) return e;
@@ -2212,18 +2228,21 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     std::unique_lock<std::mutex> lock(g_lookahead_mu);
     Lookahead* la = lookahead ? lookahead_get() : nullptr;
     bool pending = false; // side-stream work the caller's stream must join
+    bool beside = false;  // ... and it leaves XCD 0 to the next panel
     for (int64_t s0 = 0, k = 0; s0 < n; s0 += b, ++k) {
         const int nb = (int)std::min<int64_t>(b, n - s0);
         const int64_t pend = s0 + nb;
-        // the column-split panel needs its blocks resident together, which a
-        // trailing update running beside it (lookahead) could prevent
-        const bool split = !la && split_fits(n - s0);
+        // the panel chains need their blocks resident together on one XCD:
+        // the one block 0 lands on, or XCD 0 when the trailing update
+        // running beside the panel (lookahead) leaves that XCD alone
+        const bool split = split_fits(n - s0);
         if (!split) launch_head<T>(n, s0, w, stream);
         const int ept = step_ept(n - s0);
         const bool persistent = !split && ept > 0 && nb > 1;
         const ProfMark pm = prof_begin(stream, MC_PROF_PANEL);
         if (split) { // the panel's column maps are written by the kernel
-            const hipError_t e = launch_panel_split<T>(n, s0, nb, panel_view(w, k), stream);
+            const hipError_t e = launch_panel_split<T>(n, s0, nb, panel_view(w, k), stream,
+                                                       beside);
             if (e != hipSuccess) return e;
         }
         const bool single_xcd = persistent && try_panel_x<T>(n, s0, pend, w, stream);
@@ -2273,20 +2292,25 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                 hipLaunchKernelGGL((blk_trsm_mfma<T, false>), grid, dim3(kBlkThreads), lds,
                                    stream, n, s0, nb, wk);
         }
-        // with a side stream: the next panel's rows first, on the caller's
-        // stream, the rest beside the next panel; else one launch for all
-        const int64_t next = la ? std::min<int64_t>(b, rows) : rows;
-        hipError_t e = trailing(wk, update, s0, nb, pend, next, n, stream);
+        // lookahead, when the next panel is a column-split panel and the
+        // device shows all eight XCDs: the next panel's rows first, on the
+        // caller's stream, then the rest on the side stream, beside that
+        // panel and leaving XCD 0 to it (tile counter zeroed by this
+        // panel's TRSM or blk_perm).  Otherwise one launch for all rows:
+        // beside a row-per-block panel chain the update's tiles would share
+        // its XCD and slow it more than the overlap gains.
+        beside = la && la->all_xccs && split_fits(n - pend) && rows > b;
+        const int64_t next = beside ? b : rows;
+        hipError_t e = trailing(wk, update, s0, nb, pend, next, n, stream, nullptr);
         if (e != hipSuccess) return e;
         hipStream_t rest = stream;
-        if (la && rows > next) {
+        if (beside) {
             if ((e = hipEventRecord(la->fork, stream)) != hipSuccess ||
                 (e = hipStreamWaitEvent(la->side, la->fork, 0)) != hipSuccess)
                 return note_hip_error(e);
             rest = la->side;
-        }
-        if (rows > next) {
-            e = trailing(wk, update, s0, nb, pend + next, rows - next, n, rest);
+            e = trailing(wk, update, s0, nb, pend + next, rows - next, n, rest,
+                         reinterpret_cast<unsigned int*>(&w.claim[2]));
             if (e != hipSuccess) return e;
         }
         if (factor) {

@@ -124,4 +124,13 @@ __device__ __forceinline__ void comp_merge(Compensated& a, const Compensated& b)
     a.comp += b.comp;
 }
 
+// The XCD (accelerator complex) this wavefront runs on, 0..7 on a device
+// that exposes all eight.
+__device__ __forceinline__ int xcc_id()
+{
+    int x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & 0xf;
+}
+
 } // namespace mc

@@ -25,6 +25,11 @@ struct GemmArgs {
     int64_t ldu;
     const int* colsrc;
     const DevState* state;
+    // Non-null: leave XCD 0 alone (for an update running beside a panel
+    // chain there).  The blocks that land on XCD 0 leave before any memory
+    // access; the others take tiles from *tile_ctr, which must be zero at
+    // the launch, until none are left.
+    unsigned int* tile_ctr = nullptr;
 };
 
 // update: MC_UPDATE_NATIVE (FP64 MFMA for double, FP32 MFMA for float),

@@ -18,6 +18,39 @@ namespace mc {
 
 constexpr int kGemmThreads = 256;
 
+// The trailing update comes in two forms, one kernel each (a single kernel
+// with both keeps more registers live and spills):
+// - one tile per block, at blockIdx (a two-dimensional grid);
+// - beside a panel chain on XCD 0 (tile_ctr set): one resident wave of
+//   blocks, 8 W of them for W blocks resident per XCD.  Workgroups go to
+//   the XCDs in turn, so each XCD receives W.  Those on XCD 0 leave before
+//   any memory access (workgroups are dispatched in order: while one of
+//   them waits for a compute unit there, the other XCDs' blocks wait too);
+//   the others take tiles from the counter, in row-major order.  Which
+//   blocks those are does not matter for the result.
+// The tile loop: thread 0 asks for the next tile while the block works on
+// the current one.  The last barrier of a tile's K loop follows its last
+// LDS read, so the next tile may refill the buffers at once.
+template <typename T, class F>
+__device__ __forceinline__ void counter_tiles(const GemmArgs<T>& g, int bm, int bn,
+                                              F&& tile)
+{
+    __shared__ unsigned int sh_t;
+    const int64_t ntx = (g.N + bn - 1) / bn, tiles = ntx * ((g.M + bm - 1) / bm);
+    if (threadIdx.x == 0) sh_t = atomicAdd(g.tile_ctr, 1u);
+    __syncthreads();
+    int64_t t = sh_t;
+    while (t < tiles) {
+        unsigned int nt = 0;
+        if (threadIdx.x == 0) nt = atomicAdd(g.tile_ctr, 1u);
+        const int64_t ty = t / ntx;
+        tile(ty * bm, (t - ty * ntx) * bn);
+        if (threadIdx.x == 0) sh_t = nt;
+        __syncthreads();
+        t = sh_t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 / FP32: one scalar operand per lane, K = 4 per instruction.  The
 // block is WGM x WGN wavefronts, each owning TM x TN tiles of 16 x 16.  The
@@ -29,8 +62,8 @@ constexpr int kGemmThreads = 256;
 // per SIMD: WGM*WGN/2 keeps two blocks resident per compute unit (for the
 // 8-wave tile: at most 128 VGPRs).
 template <class P, int WGM, int WGN, int TM, int TN>
-__global__ void __launch_bounds__(64 * WGM * WGN, (WGM * WGN) / 2)
-gemm_scalar(GemmArgs<typename P::T> g)
+__device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
+                                            int64_t rb, int64_t cb, int tid)
 {
     using T = typename P::T;
     constexpr int NT = 64 * WGM * WGN;
@@ -40,11 +73,9 @@ gemm_scalar(GemmArgs<typename P::T> g)
     constexpr int PA = (BM * KC + NT - 1) / NT, PB = (BN * KC + NT - 1) / NT;
     __shared__ T As[2][KC][LDA]; // -L, transposed (k major)
     __shared__ T Bs[2][KC][LDB]; // U
-    if (g.state->status != kStatusOk) return;
 
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wid / WGN, wn = wid % WGN;
-    const int64_t rb = (int64_t)blockIdx.y * BM, cb = (int64_t)blockIdx.x * BN;
     const int col_in = lane & 15, kq_lane = lane >> 4;
 
     T pa[PA], pb[PB];
@@ -141,6 +172,34 @@ gemm_scalar(GemmArgs<typename P::T> g)
     }
 }
 
+// The last barrier of a tile's K loop follows its last LDS read, so the
+// next tile may refill the buffers at once.
+template <class P, int WGM, int WGN, int TM, int TN>
+__global__ void __launch_bounds__(64 * WGM * WGN, (WGM * WGN) / 2)
+gemm_scalar(GemmArgs<typename P::T> g)
+{
+    if (g.state->status != kStatusOk) return;
+    constexpr int BM = 16 * TM * WGM, BN = 16 * TN * WGN;
+    scalar_tile<P, WGM, WGN, TM, TN>(g, (int64_t)blockIdx.y * BM, (int64_t)blockIdx.x * BN,
+                                     (int)threadIdx.x);
+}
+
+template <class P, int WGM, int WGN, int TM, int TN>
+__global__ void __launch_bounds__(64 * WGM * WGN, (WGM * WGN) / 2)
+gemm_scalar_spare(GemmArgs<typename P::T> g)
+{
+    if (xcc_id() == 0) return; // the panel chain's XCD: no memory access
+    if (g.state->status != kStatusOk) return;
+    constexpr int BM = 16 * TM * WGM, BN = 16 * TN * WGN;
+    counter_tiles(g, BM, BN, [&](int64_t rb, int64_t cb) {
+        // formed afresh per tile: kept across the tile loop, the addresses
+        // derived from it would hold registers through the K loop
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        scalar_tile<P, WGM, WGN, TM, TN>(g, rb, cb, tid);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Split-BF16 x 3 with FP32 accumulation: x = hi + lo with hi = bf16(x) and
 // lo = bf16(x - hi) (round to nearest even), and
@@ -153,19 +212,17 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
 }
 
 template <int WT>
-__global__ void __launch_bounds__(kGemmThreads)
-gemm_bf16x3(GemmArgs<float> g)
+__device__ __forceinline__ void bf16x3_tile(const GemmArgs<float>& g, int64_t rb,
+                                            int64_t cb)
 {
     constexpr int BT = 32 * WT;
     constexpr int KC = 32;
     constexpr int LD = KC + 8; // bf16 elements per LDS row (16-byte aligned)
     __shared__ __attribute__((aligned(16))) __bf16 Ah[BT][LD], Al[BT][LD];
     __shared__ __attribute__((aligned(16))) __bf16 Bh[BT][LD], Bl[BT][LD];
-    if (g.state->status != kStatusOk) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid >> 1, wn = wid & 1;
-    const int64_t rb = (int64_t)blockIdx.y * BT, cb = (int64_t)blockIdx.x * BT;
     const int col_in = lane & 15, kg = lane >> 4;
 
     f4 acc[WT][WT];
@@ -236,6 +293,25 @@ gemm_bf16x3(GemmArgs<float> g)
     }
 }
 
+template <int WT>
+__global__ void __launch_bounds__(kGemmThreads)
+gemm_bf16x3(GemmArgs<float> g)
+{
+    if (g.state->status != kStatusOk) return;
+    bf16x3_tile<WT>(g, (int64_t)blockIdx.y * 32 * WT, (int64_t)blockIdx.x * 32 * WT);
+}
+
+template <int WT>
+__global__ void __launch_bounds__(kGemmThreads)
+gemm_bf16x3_spare(GemmArgs<float> g)
+{
+    if (xcc_id() == 0) return; // the panel chain's XCD: no memory access
+    if (g.state->status != kStatusOk) return;
+    counter_tiles(g, 32 * WT, 32 * WT, [&](int64_t rb, int64_t cb) {
+        bf16x3_tile<WT>(g, rb, cb);
+    });
+}
+
 // ---------------------------------------------------------------------------
 
 // Large tiles while they still give every CU work; smaller ones after.
@@ -244,12 +320,39 @@ static bool big_tiles(int64_t M, int64_t N)
     return ((M + 127) / 128) * ((N + 127) / 128) >= 512;
 }
 
-template <class Kern, class Args>
-static void launch_grid(Kern k, const Args& g, int bm, int bn, int threads,
-                        hipStream_t stream)
+// Blocks of kernel k resident on one XCD at a time (compute units per XCD
+// times blocks per compute unit); at least 1.
+template <class Kern>
+static int64_t blocks_per_xcd(Kern k, int threads)
 {
-    const dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + bm - 1) / bm));
-    hipLaunchKernelGGL(k, grid, dim3(threads), 0, stream, g);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k),
+                                                     threads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 64;
+    }
+    return std::max<int64_t>(1, (int64_t)(cus / 8) * per_cu);
+}
+
+// The update's launch: kernel `one` (a tile per block) on a two-dimensional
+// grid, or `spare` (the form beside a panel chain) on one resident wave of
+// blocks, no more than the tiles need.
+template <class Kern, class Args>
+static void launch_grid(Kern one, Kern spare, const Args& g, int bm, int bn,
+                        int threads, hipStream_t stream)
+{
+    const int64_t tx = (g.N + bn - 1) / bn, ty = (g.M + bm - 1) / bm;
+    if (g.tile_ctr) {
+        const int64_t groups = std::min<int64_t>(blocks_per_xcd(spare, threads),
+                                                 (tx * ty + 6) / 7);
+        hipLaunchKernelGGL(spare, dim3((unsigned)(8 * groups)), dim3(threads), 0,
+                           stream, g);
+    } else {
+        hipLaunchKernelGGL(one, dim3((unsigned)tx, (unsigned)ty), dim3(threads), 0,
+                           stream, g);
+    }
 }
 
 template <>
@@ -258,9 +361,11 @@ hipError_t launch_trailing_update<double>(const GemmArgs<double>& g,
 {
     if (update != MC_UPDATE_NATIVE) return hipErrorInvalidValue;
     if (big_tiles(g.M, g.N)) // 8 waves (2 x 4), 64 x 32 per wave: 128 x 128
-        launch_grid((gemm_scalar<MfmaF64, 2, 4, 4, 2>), g, 128, 128, 512, stream);
+        launch_grid(gemm_scalar<MfmaF64, 2, 4, 4, 2>, gemm_scalar_spare<MfmaF64, 2, 4, 4, 2>,
+                    g, 128, 128, 512, stream);
     else // 4 waves (2 x 2), 32 x 32 per wave: 64 x 64
-        launch_grid((gemm_scalar<MfmaF64, 2, 2, 2, 2>), g, 64, 64, 256, stream);
+        launch_grid(gemm_scalar<MfmaF64, 2, 2, 2, 2>, gemm_scalar_spare<MfmaF64, 2, 2, 2, 2>,
+                    g, 64, 64, 256, stream);
     return hipGetLastError();
 }
 
@@ -271,14 +376,16 @@ hipError_t launch_trailing_update<float>(const GemmArgs<float>& g, int update,
     const bool big = big_tiles(g.M, g.N);
     if (update == MC_UPDATE_BF16X3) {
         if (big)
-            launch_grid(gemm_bf16x3<4>, g, 128, 128, 256, stream);
+            launch_grid(gemm_bf16x3<4>, gemm_bf16x3_spare<4>, g, 128, 128, 256, stream);
         else
-            launch_grid(gemm_bf16x3<2>, g, 64, 64, 256, stream);
+            launch_grid(gemm_bf16x3<2>, gemm_bf16x3_spare<2>, g, 64, 64, 256, stream);
     } else {
         if (big)
-            launch_grid((gemm_scalar<MfmaF32, 2, 4, 4, 2>), g, 128, 128, 512, stream);
+            launch_grid(gemm_scalar<MfmaF32, 2, 4, 4, 2>, gemm_scalar_spare<MfmaF32, 2, 4, 4, 2>,
+                        g, 128, 128, 512, stream);
         else
-            launch_grid((gemm_scalar<MfmaF32, 2, 2, 2, 2>), g, 64, 64, 256, stream);
+            launch_grid(gemm_scalar<MfmaF32, 2, 2, 2, 2>, gemm_scalar_spare<MfmaF32, 2, 2, 2, 2>,
+                        g, 64, 64, 256, stream);
     }
     return hipGetLastError();
 }

@@ -164,11 +164,13 @@ def test_blocked_f32_normal(update):
         assert rel(got, ref) <= TOL_MIXED, (n, got, ref, rel(got, ref))
 
 
-@pytest.mark.parametrize("n,b", [(300, 32), (1000, 64), (1300, 128)])
+@pytest.mark.parametrize("n,b", [(300, 32), (1000, 64), (1300, 128), (5000, 128)])
 def test_lookahead_on_and_off_agree(n, b):
     """The trailing update split across two streams and the single-stream
-    schedule (the default) give the same answer, both within the FP64 bar
-    of the oracle; so does the factor call."""
+    schedule give the same answer, both within the FP64 bar of the oracle;
+    so does the factor call.  With lookahead the update beside each panel
+    leaves the panel's XCD alone (n = 5000 reaches the widest panel form
+    there)."""
     a_np = synth.normal(n, 70 + n)
     ref = O.slogdet(a_np)
     prev = mc.lookahead_enable(True)
@@ -186,6 +188,22 @@ def test_lookahead_on_and_off_agree(n, b):
     assert torch.equal(perm_on, perm_off)
     err = (lu_on - lu_off).abs().max().item()
     assert err <= 1e-10 * max(1.0, lu_off.abs().max().item()), err
+
+
+@pytest.mark.parametrize("update", ["f32", "bf16x3"])
+def test_lookahead_float_updates(update):
+    """FP32 storage with lookahead: the side-stream trailing update in its
+    FP32 and split-BF16 forms (the form that leaves the panel's XCD alone)
+    meets the mixed-precision bar of the oracle on the FP32-rounded input."""
+    n = 3000
+    a32 = synth.normal(n, 60 + n).astype(np.float32)
+    ref = O.slogdet(a32.astype(np.float64))
+    prev = mc.lookahead_enable(True)
+    try:
+        got = run(a32, 128, update=update, dtype=torch.float32)
+    finally:
+        mc.lookahead_enable(prev)
+    assert_parity(got, ref, TOL_MIXED)
 
 
 @pytest.mark.parametrize("n,b,dtype", [(2500, 128, torch.float64),
