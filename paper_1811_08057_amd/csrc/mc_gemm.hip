@@ -314,10 +314,166 @@ gemm_bf16x3_spare(GemmArgs<float> g)
 
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Updates of 65..128 rows (the next panel's rows),
+// FP64 or FP32 operands, K <= kMaxPanel.  Too few tiles to hide latency
+// behind other blocks, so a block keeps everything in flight at once:
+// - its whole K of -L and U goes to LDS from one round of 16-byte loads,
+//   issued with the reads of the old C (through colsrc);
+// - each of the four wavefronts takes a quarter of K for the whole 64 x 64
+//   tile (16 independent accumulators, chains of K/16 products, where one
+//   wavefront per 32 x 32 quarter would chain K/4 dependent products);
+// - the four partial tiles are summed through LDS, each wavefront then
+//   finishing 16 rows.
+// One block per compute unit.
+template <class P>
+__global__ void __launch_bounds__(256, 1)
+gemm_rows(GemmArgs<typename P::T> g)
+{
+    using T = typename P::T;
+    constexpr int BT = 64, KM = (int)kMaxPanel;
+    constexpr int LD = BT + (sizeof(T) == 8 ? 8 : 16); // both tiles in 160 KB
+    constexpr int V = 16 / sizeof(T);                  // elements per 16 bytes
+    constexpr int PE = BT * KM / (256 * V);            // 16-byte loads per tile
+    constexpr int RL = BT + (sizeof(T) == 8 ? 2 : 4);  // partial-tile row pitch
+    static_assert(4 * BT * RL <= 2 * KM * LD, "partials fit in the operand space");
+    __shared__ T lds[2 * KM * LD];
+    T (*As)[LD] = reinterpret_cast<T (*)[LD]>(lds);           // -L, k major
+    T (*Bs)[LD] = reinterpret_cast<T (*)[LD]>(lds + KM * LD); // U
+    if (g.state->status != kStatusOk) return;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col_in = lane & 15;
+    const int64_t rb = (int64_t)blockIdx.y * BT, cb = (int64_t)blockIdx.x * BT;
+    const int K = g.K;
+    typedef T tv __attribute__((ext_vector_type(V)));
+
+    // the finishing rows of this thread: row fr + 4 q (q = 0..3) of its
+    // wavefront's 16, column fc; their old C (through colsrc) first
+    const int fr = wid * 16 + (lane >> 4), fc = (lane & 15) * 4;
+    int64_t src[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t col = cb + fc + q;
+        src[q] = col < g.N ? g.colsrc[g.c0 + col] : 0;
+    }
+    // 16-byte loads where the rows are 16-byte aligned (the blocked path's
+    // L and W are; a caller's matrix need not be)
+    const bool lvec = ((reinterpret_cast<uintptr_t>(g.L) |
+                        (uintptr_t)g.ldl * sizeof(T)) & 15) == 0;
+    const bool uvec = ((reinterpret_cast<uintptr_t>(g.U + g.c0) |
+                        (uintptr_t)g.ldu * sizeof(T)) & 15) == 0;
+    tv pa[PE], pb[PE];
+#pragma unroll
+    for (int p = 0; p < PE; ++p) {
+        const int e = (tid + 256 * p) * V;
+        const int rr = e / KM, kk = e % KM; // L: rows of K contiguous
+        const int64_t row = rb + rr;
+        if (lvec && row < g.M && kk + V <= K) {
+            pa[p] = *reinterpret_cast<const tv*>(g.L + row * g.ldl + kk);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                pa[p][v] = (row < g.M && kk + v < K) ? g.L[row * g.ldl + kk + v] : T(0);
+        }
+        const int kb = e / BT, cc = e % BT; // U: K rows of 64 columns
+        const int64_t col = cb + cc;
+        const T* up = g.U + (int64_t)kb * g.ldu + g.c0 + col;
+        if (uvec && kb < K && col + V <= g.N) {
+            pb[p] = *reinterpret_cast<const tv*>(up);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) pb[p][v] = (kb < K && col + v < g.N) ? up[v] : T(0);
+        }
+    }
+    T cold[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t row = rb + fr + 4 * r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            cold[r][q] = (row < g.M && cb + fc + q < g.N)
+                             ? g.C[(g.r0 + row) * g.ldc + src[q]]
+                             : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < PE; ++p) {
+        const int e = (tid + 256 * p) * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            As[(e + v) % KM][(e + v) / KM] = -pa[p][v];
+            Bs[(e + v) / BT][(e + v) % BT] = pb[p][v];
+        }
+    }
+    __syncthreads();
+
+    // this wavefront's quarter of K (entries past K are zero)
+    typename P::Acc acc[4][4];
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[ti][tj][r] = T(0);
+    const int kq_lane = lane >> 4, kspan = ((K + 15) / 16) * 4;
+    const int k0 = wid * kspan, k1 = k0 + kspan;
+    for (int kq = k0; kq < k1; kq += 4) {
+        T a[4], b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            a[t] = As[kq + kq_lane][t * 16 + col_in];
+            b[t] = Bs[kq + kq_lane][t * 16 + col_in];
+        }
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = P::mma(a[ti], b[tj], acc[ti][tj]);
+    }
+    __syncthreads(); // the operands are no longer read: partials go there
+    T* part = lds + wid * BT * RL;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                part[(ti * 16 + P::drow(lane, r)) * RL + tj * 16 + col_in] = acc[ti][tj][r];
+    __syncthreads();
+
+    // C[dst] = C[src] + the four partials (a moved column's source lies in
+    // the panel's column range, which no block writes; src == dst otherwise)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t row = rb + fr + 4 * r;
+        if (row >= g.M) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t col = cb + fc + q;
+            if (col >= g.N) continue;
+            const int o = (fr + 4 * r) * RL + fc + q;
+            T v = cold[r][q];
+#pragma unroll
+            for (int w4 = 0; w4 < 4; ++w4) v += lds[w4 * BT * RL + o];
+            g.C[(g.r0 + row) * g.ldc + g.c0 + col] = v;
+        }
+    }
+}
+
 // Large tiles while they still give every CU work; smaller ones after.
 static bool big_tiles(int64_t M, int64_t N)
 {
     return ((M + 127) / 128) * ((N + 127) / 128) >= 512;
+}
+
+// gemm_rows: 65..128 rows (the next panel's) and K <= kMaxPanel, not beside
+// a panel chain.  (Measured at N = 7867, K = 128: 22.0 against 24.7 us for
+// 128 rows with gemm_scalar's 64 x 64 tiles; below 64 rows gemm_scalar is
+// the faster, 17.5 against 20.3 us at 37 rows.)
+template <typename T>
+static bool rows_form(const GemmArgs<T>& g)
+{
+    return !g.tile_ctr && g.M > 64 && g.M <= 128 && g.K <= kMaxPanel;
 }
 
 // Blocks of kernel k resident on one XCD at a time (compute units per XCD
@@ -360,6 +516,12 @@ hipError_t launch_trailing_update<double>(const GemmArgs<double>& g,
                                           int update, hipStream_t stream)
 {
     if (update != MC_UPDATE_NATIVE) return hipErrorInvalidValue;
+    if (rows_form(g)) {
+        hipLaunchKernelGGL(gemm_rows<MfmaF64>, dim3((unsigned)((g.N + 63) / 64),
+                                                    (unsigned)((g.M + 63) / 64)),
+                           dim3(256), 0, stream, g);
+        return hipGetLastError();
+    }
     if (big_tiles(g.M, g.N)) // 8 waves (2 x 4), 64 x 32 per wave: 128 x 128
         launch_grid(gemm_scalar<MfmaF64, 2, 4, 4, 2>, gemm_scalar_spare<MfmaF64, 2, 4, 4, 2>,
                     g, 128, 128, 512, stream);
@@ -379,6 +541,10 @@ hipError_t launch_trailing_update<float>(const GemmArgs<float>& g, int update,
             launch_grid(gemm_bf16x3<4>, gemm_bf16x3_spare<4>, g, 128, 128, 256, stream);
         else
             launch_grid(gemm_bf16x3<2>, gemm_bf16x3_spare<2>, g, 64, 64, 256, stream);
+    } else if (rows_form(g)) {
+        hipLaunchKernelGGL(gemm_rows<MfmaF32>, dim3((unsigned)((g.N + 63) / 64),
+                                                    (unsigned)((g.M + 63) / 64)),
+                           dim3(256), 0, stream, g);
     } else {
         if (big)
             launch_grid(gemm_scalar<MfmaF32, 2, 4, 4, 2>, gemm_scalar_spare<MfmaF32, 2, 4, 4, 2>,
