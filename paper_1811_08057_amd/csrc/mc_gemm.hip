@@ -62,7 +62,9 @@ __device__ __forceinline__ void counter_tiles(const GemmArgs<T>& g, int bm, int 
 // also hold the tile's old C, read inside the K loop (PF) so that the
 // epilogue waits on no load: 32.4 against 29.4 TFLOP/s for 8 wavefronts of
 // 64 x 32 with C read in the epilogue (M = 7744, N = 7872, K = 128), and
-// 27.4 against 22.9 on the seven XCDs beside a panel chain.
+// 27.4 against 22.9 on the seven XCDs beside a panel chain.  In FP32 the
+// same 16 wavefronts fit twice per compute unit without C (49 VGPRs), which
+// is faster still: 65.7 against 56.0 TFLOP/s with C and 51.2 for 8.
 template <class P, int WGM, int WGN, int TM, int TN, bool PF>
 __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
                                             int64_t rb, int64_t cb, int tid)
@@ -571,9 +573,9 @@ hipError_t launch_trailing_update<float>(const GemmArgs<float>& g, int update,
                                                     (unsigned)((g.M + 63) / 64)),
                            dim3(256), 0, stream, g);
     } else {
-        if (big)
-            launch_grid(gemm_scalar<MfmaF32, 2, 4, 4, 2, 4, false>,
-                        gemm_scalar_spare<MfmaF32, 2, 4, 4, 2, 4, false>, g, 128, 128, 512,
+        if (big) // 16 waves of 32 x 32, two blocks per compute unit
+            launch_grid(gemm_scalar<MfmaF32, 4, 4, 2, 2, 4, false>,
+                        gemm_scalar_spare<MfmaF32, 4, 4, 2, 2, 4, false>, g, 128, 128, 1024,
                         stream);
         else
             launch_grid(gemm_scalar<MfmaF32, 2, 2, 2, 2, 2, false>,
