@@ -257,12 +257,22 @@ def _dtype_of(t) -> int:
 
 class BatchedPlan:
     """Device-side description of a batch (pointer, size and stride arrays,
-    workspace, results) for mc_logdet_batched.  The matrices must stay alive
-    and in place while the plan is used.  ``run()`` enqueues the call on the
-    current stream; ``capture()`` records it into a hipGraph (through
-    torch.cuda.CUDAGraph) that ``replay()`` launches."""
+    workspaces, results).  The matrices must stay alive and in place while
+    the plan is used.  ``run()`` enqueues the calls on the current stream;
+    ``capture()`` records them into a hipGraph (through torch.cuda.CUDAGraph)
+    that ``replay()`` launches.
 
-    def __init__(self, mats, b: int = -1, update="native"):
+    Members of at least ``blocked_min_n`` rows go through the single-matrix
+    blocked path (mc_logdet, one after another, sharing one workspace), the
+    rest through one persistent mc_logdet_batched launch: the batched kernel
+    condenses each matrix in one workgroup, which for the largest members
+    takes longer than the whole-GPU blocked path does for all of them.
+    ``blocked_min_n=None`` keeps every member in the batched launch."""
+
+    BLOCKED_MIN_N = 1024
+
+    def __init__(self, mats, b: int = -1, update="native",
+                 blocked_min_n: Optional[int] = BLOCKED_MIN_N):
         if not mats:
             raise ValueError("empty batch")
         dev = mats[0].device
@@ -277,28 +287,53 @@ class BatchedPlan:
         self.b = b
         self.update = _update_code(update)
         self.batch = len(mats)
-        self.n_max = max(m.shape[0] for m in mats)
-        ptrs = [m.data_ptr() for m in mats]
         ns = [m.shape[0] for m in mats]
-        ldas = [_square_rows(m) for m in mats]
-        self.ptrs = torch.tensor(ptrs, dtype=torch.int64, device=dev)
-        self.ns = torch.tensor(ns, dtype=torch.int64, device=dev)
-        self.ldas = torch.tensor(ldas, dtype=torch.int64, device=dev)
-        nb = lib().mc_logdet_batched_workspace(self.batch, self.n_max,
-                                               _dtype_of(dt), self.update, b)
-        if nb == 0:
-            raise MCError("unsupported combination for the batched path")
-        self.work = torch.empty(nb, dtype=torch.uint8, device=dev)
-        self.result = new_result(dev, self.batch)
+        self.large = [i for i, n in enumerate(ns)
+                      if blocked_min_n is not None and n >= blocked_min_n]
+        big = set(self.large)
+        self.small = [i for i in range(self.batch) if i not in big]
+        self.result = new_result(dev, self.batch)  # the large members' slots
+        self.blocked_work = None
+        if self.large:
+            n_big = max(ns[i] for i in self.large)
+            nb = lib().mc_logdet_workspace(n_big, _dtype_of(dt), self.update, -1)
+            if nb == 0:
+                raise MCError("unsupported combination for the blocked path")
+            self.blocked_work = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.n_max = max([ns[i] for i in self.small], default=0)
+        if self.small:
+            sm = [mats[i] for i in self.small]
+            self.ptrs = torch.tensor([m.data_ptr() for m in sm], dtype=torch.int64,
+                                     device=dev)
+            self.ns = torch.tensor([m.shape[0] for m in sm], dtype=torch.int64,
+                                   device=dev)
+            self.ldas = torch.tensor([_square_rows(m) for m in sm], dtype=torch.int64,
+                                     device=dev)
+            nb = lib().mc_logdet_batched_workspace(len(sm), self.n_max,
+                                                   _dtype_of(dt), self.update, b)
+            if nb == 0:
+                raise MCError("unsupported combination for the batched path")
+            self.work = torch.empty(nb, dtype=torch.uint8, device=dev)
+            self.small_result = new_result(dev, len(sm))
         self.graph = None
 
     def run(self, stream: Optional[torch.cuda.Stream] = None) -> None:
-        st = lib().mc_logdet_batched(
-            self.ptrs.data_ptr(), self.ns.data_ptr(), self.ldas.data_ptr(),
-            self.batch, self.n_max, _dtype_of(self.dtype), self.update, self.b,
-            self.result.data_ptr(), self.work.data_ptr(), self.work.numel(),
-            _stream_ptr(stream, self.device))
-        _check(st, "mc_logdet_batched")
+        sp = _stream_ptr(stream, self.device)
+        for i in self.large:
+            m = self.mats[i]
+            st = lib().mc_logdet(m.data_ptr(), m.shape[0], _square_rows(m),
+                                 _dtype_of(self.dtype), self.update, -1,
+                                 self.result[i:i + 1].data_ptr(),
+                                 self.blocked_work.data_ptr(),
+                                 self.blocked_work.numel(), sp)
+            _check(st, "mc_logdet")
+        if self.small:
+            st = lib().mc_logdet_batched(
+                self.ptrs.data_ptr(), self.ns.data_ptr(), self.ldas.data_ptr(),
+                len(self.small), self.n_max, _dtype_of(self.dtype), self.update,
+                self.b, self.small_result.data_ptr(), self.work.data_ptr(),
+                self.work.numel(), sp)
+            _check(st, "mc_logdet_batched")
 
     def capture(self) -> None:
         self.run()  # warm-up outside the capture (kernel attributes)
@@ -314,7 +349,11 @@ class BatchedPlan:
         self.graph.replay()
 
     def results(self) -> list:
-        return read_result(self.result)
+        out = read_result(self.result)
+        if self.small:
+            for i, r in zip(self.small, read_result(self.small_result)):
+                out[i] = r
+        return out
 
 
 def logdet_batched(mats, b: int = -1, update="native") -> list:
