@@ -233,8 +233,8 @@ mc_status mc_autotune_batched(int dtype, int update, int64_t n_max_tune,
  * off, run each kernel on the caller's stream.  Both schedules give the
  * same pivots and factors.  Returns the previous setting (1 on, 0 off).
  * Process-wide; calls that enqueue blocked work are serialised on a lock
- * while they do.  (Measured on MI355X at N = 8000, FP64: 26.7 ms on,
- * 33.3 ms off.)
+ * while they do.  (Measured on MI355X at N = 8000, FP64: 24.7 ms on,
+ * 33.2 ms off.)
  */
 int mc_lookahead_enable(int on);
 
