@@ -1,11 +1,16 @@
 // mc_gemm.hip -- MFMA kernels for the blocked path's trailing update.
 //
-// Block tile BT x BT of C (BT = 32 * WT), four wavefronts in a 2 x 2 grid,
-// each owning WT x WT tiles of 16 x 16.  -L and U stream through LDS in K
-// chunks into accumulators that start from zero; the epilogue adds the old
-// C (read through colsrc) and stores in place.  Per block: 2 * BT^2 * K
-// flops against BT^2 * 2 * sizeof(T) bytes of C traffic, so the update is
-// matrix-core bound once K = b is large enough (b/8 flop per byte in FP64).
+// Block tile BT x BT of C (128 x 128, or 64 x 64 once too few tiles remain),
+// a grid of wavefronts each owning a few 16 x 16 tiles.  -L and U stream
+// through LDS in K chunks into accumulators that start from zero; the old C
+// (read through colsrc, in the K loop or the epilogue) is added and the
+// result stored in place.  Per block: 2 * BT^2 * K flops against
+// BT^2 * 2 * sizeof(T) bytes of C traffic, so the update is matrix-core
+// bound once K = b is large enough (b/8 flop per byte in FP64).  Three
+// launch forms: a tile per block (`gemm_scalar`, `gemm_bf16x3`); beside a
+// panel chain, a resident wave of blocks taking tiles from a counter off
+// XCD 0 (`*_spare`); and the next panel's rows, every operand staged at
+// once (`gemm_rows`).
 //
 // Operand and accumulator layouts: mc_mfma.h.
 #include "mc_gemm.h"
@@ -16,7 +21,6 @@
 
 namespace mc {
 
-constexpr int kGemmThreads = 256;
 
 // The trailing update comes in two forms, one kernel each (a single kernel
 // with both keeps more registers live and spills):
