@@ -9,8 +9,24 @@
 #include "mc_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads for the row updates of one condensation step (1 = serial).
+ * Figure 6 hands the rows of a step to different processes; here they go to
+ * OpenMP threads.  Every row's arithmetic is the same with any count, so
+ * the results do not depend on it. */
+static int g_threads = 1;
+
+int mco_set_threads(int threads)
+{
+    const int prev = g_threads;
+    g_threads = threads < 1 ? 1 : threads;
+    return prev;
+}
+
+int mco_num_procs(void) { return omp_get_num_procs(); }
 
 /* Compensated (Neumaier) running sum of log|pivot| (Figure 6, step 4.4
  * accumulates log|pivot|; the compensation keeps the sum to ~1 ulp). */
@@ -112,11 +128,24 @@ static int build_row_order(int64_t n, int policy, const int64_t* given,
     return 0;
 }
 
+/* Relative margin of the chosen pivot over the runner-up in its row:
+ * (|p| - max over the other active slots of |a|) / |p|; 1 when no other
+ * slot is active.  0 means a tie that only the tie rule decided. */
+static double pivot_gap(const double* row, int64_t m, int64_t l)
+{
+    double second = 0.0;
+    for (int64_t j = 0; j < m; ++j)
+        if (j != l && fabs(row[j]) > second) second = fabs(row[j]);
+    const double a = fabs(row[l]);
+    return (a - second) / a;
+}
+
 static int slogdet_impl(const double* A, int64_t n, int64_t lda,
                         int row_policy, const int64_t* row_order,
                         int64_t n_virt, int col_rule, int64_t max_steps,
                         mco_result* out, int32_t* piv_row_out,
-                        int32_t* piv_col_out, double* piv_val_out)
+                        int32_t* piv_col_out, double* piv_val_out,
+                        double* piv_gap_out)
 {
     if (!out) return -8;
     if (n < 0) return -2;
@@ -189,6 +218,7 @@ static int slogdet_impl(const double* A, int64_t n, int64_t lda,
         piv_row[s] = (int32_t)k;
         piv_col[s] = colid[l];
         if (piv_val_out) piv_val_out[s] = p;
+        if (piv_gap_out) piv_gap_out[s] = pivot_gap(row, m, l);
         neumaier_add(&logsum, log(fabs(p)));
         if (p < 0.0) ++negatives;
         live[k] = 0;
@@ -203,6 +233,7 @@ static int slogdet_impl(const double* A, int64_t n, int64_t lda,
         /* Steps 4.8-4.11 for every live row: stash the multiplier a_il,
          * move the last slot into slot l, then form
          * B*_ij = a_ij - a_il * (a_kj / a_kl)  (Eq. 3 with Eq. 2). */
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1 && m > 32)
         for (int64_t i = 0; i < n; ++i) {
             if (!live[i]) continue;
             double* wi = W + i * n;
@@ -267,14 +298,21 @@ int mco_slogdet(const double* A, int64_t n, int64_t lda, int row_policy,
                 double* piv_val)
 {
     return slogdet_impl(A, n, lda, row_policy, row_order, n_virt, col_rule, 0,
-                        out, piv_row, piv_col, piv_val);
+                        out, piv_row, piv_col, piv_val, NULL);
+}
+
+int mco_slogdet_gaps(const double* A, int64_t n, int64_t lda, mco_result* out,
+                     int32_t* piv_col, double* piv_gap)
+{
+    return slogdet_impl(A, n, lda, MCO_ROWS_TOP_DOWN, NULL, 0, MCO_COL_MAXABS, 0,
+                        out, NULL, piv_col, NULL, piv_gap);
 }
 
 int mco_slogdet_steps(const double* A, int64_t n, int64_t lda,
                       int64_t max_steps, mco_result* out)
 {
     return slogdet_impl(A, n, lda, MCO_ROWS_TOP_DOWN, NULL, 0, MCO_COL_MAXABS,
-                        max_steps, out, NULL, NULL, NULL);
+                        max_steps, out, NULL, NULL, NULL, NULL);
 }
 
 /* 2 x 2 determinant of [[a, b], [c, d]]. */
@@ -349,6 +387,7 @@ int mco_inverse(const double* A, int64_t n, int64_t lda, double* Ainv,
             }
         const double d = M[c * w + c];
         for (int64_t j = 0; j < w; ++j) M[c * w + j] = M[c * w + j] / d;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1 && n > 32)
         for (int64_t i = 0; i < n; ++i) {
             if (i == c) continue;
             const double f = M[i * w + c];

@@ -62,6 +62,22 @@ int mco_slogdet(const double* A, int64_t n, int64_t lda, int row_policy,
                 mco_result* out, int32_t* piv_row, int32_t* piv_col,
                 double* piv_val);
 
+/* As mco_slogdet with top-down rows and the max-|a| rule; piv_gap[s]
+ * (optional, n entries) receives the relative margin of step s's pivot over
+ * the runner-up in its row, (|p| - |a_second|) / |p| (1 when the row has one
+ * active slot, 0 for a tie decided by the tie rule).  A test that compares
+ * another implementation's pivot sequence with this one's can use it to see
+ * whether rounding alone could change a choice. */
+int mco_slogdet_gaps(const double* A, int64_t n, int64_t lda, mco_result* out,
+                     int32_t* piv_col, double* piv_gap);
+
+/* Threads for the row updates of each step (OpenMP; default 1).  Results
+ * do not depend on the count.  Returns the previous setting. */
+int mco_set_threads(int threads);
+
+/* Processors OpenMP sees on this host. */
+int mco_num_procs(void);
+
 /* As mco_slogdet (top-down rows, max-|a| rule) but stops after max_steps
  * condensation steps; used only to time a bounded sample.  info is
  * MCO_INFO_PARTIAL when the limit was reached. */

@@ -31,7 +31,7 @@ INFO_PARTIAL = -2
 
 # Plain build: contraction off so products and differences round separately.
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-          "-shared"]
+          "-fopenmp", "-shared"]
 
 
 def build(force: bool = True) -> str:
@@ -85,6 +85,12 @@ def lib():
         L.mco_inverse.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, dp,
                                   ctypes.c_int64]
         L.mco_inverse.restype = ctypes.c_int
+        L.mco_slogdet_gaps.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.POINTER(_Result), i32p, dp]
+        L.mco_slogdet_gaps.restype = ctypes.c_int
+        L.mco_set_threads.argtypes = [ctypes.c_int]
+        L.mco_set_threads.restype = ctypes.c_int
+        L.mco_num_procs.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -126,6 +132,33 @@ def slogdet(a: np.ndarray, rows: int = ROWS_TOP_DOWN,
         return SlogdetResult(res.sign, res.logabsdet, res.info, pr[:n], pc[:n],
                              pv[:n])
     return SlogdetResult(res.sign, res.logabsdet, res.info)
+
+
+def slogdet_gaps(a: np.ndarray):
+    """(SlogdetResult with piv_col, gaps): the top-down, largest-|a| run with
+    each step's relative margin of the pivot over the runner-up in its row
+    (0 = a tie the tie rule decided, 1 = a single active slot)."""
+    a = _as_f64(a)
+    n = a.shape[0]
+    pc = np.zeros(max(n, 1), np.int32)
+    gap = np.full(max(n, 1), np.nan)
+    res = _Result()
+    rc = lib().mco_slogdet_gaps(_ptr(a, ctypes.c_double), n, max(n, 1),
+                                ctypes.byref(res), _ptr(pc, ctypes.c_int32),
+                                _ptr(gap, ctypes.c_double))
+    if rc != 0:
+        raise ValueError(f"mco_slogdet_gaps rejected its arguments ({rc})")
+    return SlogdetResult(res.sign, res.logabsdet, res.info, None, pc[:n]), gap[:n]
+
+
+def set_threads(threads: int) -> int:
+    """OpenMP threads for the row updates of each step; returns the previous
+    count.  The results do not depend on it."""
+    return int(lib().mco_set_threads(int(threads)))
+
+
+def num_procs() -> int:
+    return int(lib().mco_num_procs())
 
 
 def slogdet_steps(a: np.ndarray, max_steps: int) -> SlogdetResult:

@@ -85,3 +85,54 @@ def perm_parity_inversions(p: Sequence[int]) -> int:
 
 def log_abs_int(d: int) -> float:
     return math.log(abs(d))
+
+
+def crout_lu_rows(m: Sequence[Sequence], cols: Sequence[int]):
+    """Exact LU without pivoting of the column-permuted matrix A[:, cols]:
+    A[:, cols] = L U, L lower triangular (its diagonal holds the pivots),
+    U unit upper triangular.  Rows are taken top to bottom.  Returns
+    (pivots, U) with Fractions, or None if a zero pivot appears.  A
+    textbook elimination, independent of condensation and of any pivot
+    rule: the caller supplies the column order to be checked."""
+    n = len(m)
+    a = [[Fraction(m[i][c]) for c in cols] for i in range(n)]
+    piv, urows = [], []
+    for s in range(n):
+        p = a[s][s]
+        if p == 0:
+            return None
+        piv.append(p)
+        urow = [Fraction(0)] * n
+        urow[s] = Fraction(1)
+        for j in range(s + 1, n):
+            urow[j] = a[s][j] / p
+        urows.append(urow)
+        for i in range(s + 1, n):
+            f = a[i][s]
+            if f == 0:
+                continue
+            for j in range(s + 1, n):
+                a[i][j] -= f * urow[j]
+    return piv, urows
+
+
+def satisfies_maxabs_rule(m: Sequence[Sequence], cols: Sequence[int]) -> bool:
+    """True iff `cols` is the pivot-column sequence of the largest-|a| rule
+    with ties to the smallest original column, rows top to bottom: in the
+    exact factorisation A[:, cols] = L U (crout_lu_rows) every |U[s][j]| <= 1
+    (the pivot is a largest entry of its condensed row) and |U[s][j]| == 1
+    only where cols[s] < cols[j] (a tie goes to the smaller original index).
+    Those conditions fix the sequence uniquely, one step at a time."""
+    n = len(m)
+    if sorted(cols) != list(range(n)):
+        return False
+    f = crout_lu_rows(m, cols)
+    if f is None:
+        return False
+    _, u = f
+    for s in range(n):
+        for j in range(s + 1, n):
+            a = abs(u[s][j])
+            if a > 1 or (a == 1 and cols[s] > cols[j]):
+                return False
+    return True

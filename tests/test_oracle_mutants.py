@@ -49,6 +49,16 @@ MUTANTS = {
                             "M[i * w + j] = M[i * w + j] + prod;"),
     "log_not_abs_sum": ("neumaier_add(&logsum, log(fabs(p)));",
                         "neumaier_add(&logsum, log(fabs(p)) * 0.5);"),
+    # the compensation dropped: a plain running sum (Figure 6 step 4.4 as
+    # printed), which the cancelling-diagonal pin must tell apart
+    "plain_log_sum": ("static void neumaier_add(neumaier* a, double x)\n{",
+                      "static void neumaier_add(neumaier* a, double x)\n{\n"
+                      "    a->sum += x;\n    return;"),
+    # ties to the smallest current slot instead of the smallest original
+    # column: the same at step 0, different once slots have moved
+    "tie_smallest_slot": (
+        "(key == bestkey && colid[j] < colid[best])) {\n                best = j;\n                bestkey = key;\n            }\n        } else if (rule == MCO_COL_FIRST_NONZERO)",
+        "(key == bestkey && j < best)) {\n                best = j;\n                bestkey = key;\n            }\n        } else if (rule == MCO_COL_FIRST_NONZERO)"),
 }
 
 
@@ -110,6 +120,17 @@ def _battery():
     z = synth.uniform(7, 1)
     z[3] = 0
     check("singular", O.slogdet(z).info == 4)
+    # pivot sequence on exact ties: the exact characterisation of the rule
+    for seed in range(3):
+        u = synth.unimodular_ties(20, 50 + seed)
+        cols = [int(c) for c in O.slogdet(u, pivots=True).piv_col]
+        check(f"unimodular_rule.{seed}",
+              exact.satisfies_maxabs_rule(u.astype(int).tolist(), cols))
+    # compensated log sum on a cancelling diagonal
+    from tests.test_oracle_pivots import cancelling_diagonal
+    cd, dd = cancelling_diagonal()
+    want = math.fsum(math.log(abs(x)) for x in dd)
+    check("compensated_sum", abs(O.slogdet(cd).logabsdet - want) <= 4e-16 * max(1.0, abs(want)))
     # explicit inverse vs closed form
     a, d, _ = synth.householder_qd(12, 7, 2)
     check("inverse", np.allclose(O.inverse(a), (a / d[None, :] ** 2).T,
