@@ -11,7 +11,12 @@ named in the Abstract):
 * ``uniform(n, seed)``   -- i.i.d. U[-1, 1] entries.
 * ``normal(n, seed)``    -- i.i.d. N(0, 1) entries.
 * ``wishart(n, rng)``    -- A = X^T X / m + 1e-3 I, X of shape (m, n) with
-  i.i.d. N(0, 1) entries and m = 2n, symmetrised as (A + A^T)/2.
+  i.i.d. N(0, 1) entries and m = 2n.  The draws are rounded to multiples of
+  2^-12 (and clipped to |x| <= 8, which a draw passes with probability
+  1 - 1e-15), so every product x_ki x_kj is a multiple of 2^-24 below 2^6
+  and any sum of up to 2^15 of them is exact in FP64: X^T X comes out the
+  same bytes on any host or device and in any summation order.  The
+  division by m and the ridge are single IEEE operations.
 * ``wishart_batch``      -- sizes drawn uniformly in [lo, hi] from one
   generator, then one Wishart matrix per size from the same generator.
 
@@ -46,23 +51,32 @@ def normal(n: int, seed: int) -> np.ndarray:
     return out
 
 
+GRID = 1.0 / 4096.0  # spacing of the Wishart draws (2^-12)
+CLIP = 8.0
+
+
 def wishart_from(g: np.random.Generator, n: int, m_factor: int = 2,
                  ridge: float = RIDGE, gram=None) -> np.ndarray:
-    """A = X^T X / m + ridge * I with X (m x n) ~ N(0,1), m = m_factor * n.
+    """A = X^T X / m + ridge * I with X (m x n) ~ N(0,1) on the 2^-12 grid,
+    m = m_factor * n.
 
     ``gram`` (optional) computes X^T X for a float64 array X; the default is
-    numpy.  Only the product differs between callers, never the draws.
+    numpy.  On the grid the product is exact, so every caller gets the same
+    bytes; only where it runs differs.
     """
     m = m_factor * n
+    if m > (1 << 15):
+        raise ValueError("the exact-Gram bound holds for m <= 2^15 rows")
     x = np.empty((m, n), dtype=np.float64)
     chunk = max(1, (1 << 24) // max(n, 1))
     for r0 in range(0, m, chunk):
         r1 = min(m, r0 + chunk)
-        x[r0:r1] = g.standard_normal((r1 - r0, n))
+        d = g.standard_normal((r1 - r0, n))
+        np.clip(d, -CLIP, CLIP, out=d)
+        x[r0:r1] = np.round(d / GRID) * GRID
     a = gram(x) if gram is not None else x.T @ x
     a = np.asarray(a, dtype=np.float64)
     a /= m
-    a = 0.5 * (a + a.T)
     a[np.diag_indices(n)] += ridge
     return a
 
@@ -84,6 +98,31 @@ def wishart_batch(count: int, lo: int, hi: int, seed: int,
 def int_matrix(n: int, seed: int, lo: int = -9, hi: int = 9) -> np.ndarray:
     """Integer-valued matrix (stored as FP64) with entries in [lo, hi]."""
     return rng(seed).integers(lo, hi + 1, size=(n, n)).astype(np.float64)
+
+
+def unimodular_ties(n: int, seed: int, reach: int = 0) -> np.ndarray:
+    """A totally unimodular n x n matrix with |det| = 1 and many exact ties.
+
+    Built as D1 P U Q D2: U upper triangular with ones on the diagonal and
+    row i holding ones on columns i .. r_i (an interval, r_i - i uniform in
+    0 .. reach, reach = n // 4 by default), P and Q random permutations and
+    D1, D2 random +-1 diagonals.  Interval matrices are totally unimodular,
+    and permutations and sign changes keep that, as does pivoting on a +-1
+    entry, so every condensed row holds only -1, 0 and 1: each pivot is +-1
+    and is tied with every other non-zero of its row.  The arithmetic is
+    exact in any floating-point format and any summation order.
+    """
+    g = rng(seed)
+    reach = max(1, n // 4) if reach <= 0 else reach
+    u = np.zeros((n, n), dtype=np.float64)
+    for i in range(n):
+        r = min(n - 1, i + int(g.integers(0, reach + 1)))
+        u[i, i:r + 1] = 1.0
+    p = g.permutation(n)
+    q = g.permutation(n)
+    d1 = np.where(g.random(n) < 0.5, -1.0, 1.0)
+    d2 = np.where(g.random(n) < 0.5, -1.0, 1.0)
+    return (d1[:, None] * u[p][:, q]) * d2[None, :]
 
 
 def householder_qd(n: int, seed: int, reflectors: int, dlo: float = 0.5,
@@ -115,6 +154,17 @@ CONFIGS = {
     "wishart_batch512": dict(kind="wishart_batch", count=512, lo=32, hi=1024, seed=4),
     "wishart_batch64": dict(kind="wishart_batch", count=64, lo=256, hi=2048, seed=5),
 }
+
+
+def sha256_of(mats) -> str:
+    """SHA-256 of the C-ordered bytes of a matrix, or of a list of matrices
+    one after another: the identity of a workload input."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for m in (mats if isinstance(mats, (list, tuple)) else [mats]):
+        h.update(np.ascontiguousarray(m).tobytes())
+    return h.hexdigest()
 
 
 def make(name: str, **kw):
