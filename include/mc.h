@@ -29,8 +29,21 @@
  *   - Results: a singular matrix (an all-zero pivot row at 0-based step s)
  *     gives {logabsdet = -inf, sign = 0, info = s + 1}; a NaN or Inf in a
  *     pivot row gives {NaN, 0, MC_INFO_NONFINITE}; n = 0 gives {0, +1, 0}.
- *   - Concurrent calls are safe on different streams with different
- *     workspaces; calls that share a workspace must be stream-ordered.
+ *   - Concurrency.  Calls on different streams need different workspaces;
+ *     calls that share a workspace must be stream-ordered.  Blocked-path
+ *     calls (mc_logdet / mc_logdet_pivots with b != 0, mc_logdet_factor and
+ *     the calls built on it) run one after another on the GPU per device,
+ *     whatever streams they are enqueued on: each waits for an event the
+ *     device's previous blocked call recorded after its last kernel,
+ *     because a column-split panel (below) needs all of its blocks resident
+ *     together on one XCD and two panels at once would contend for them.
+ *     Calls enqueued under graph capture are not ordered that way; a
+ *     replayed graph must not overlap another blocked call on its device.
+ *     A foreign kernel that holds the panel XCD's compute units for more
+ *     than a second makes the call end with MC_INFO_ABORTED (its bounded
+ *     waits run out) rather than hang.  The plain and batched paths keep
+ *     no such state.  Process-wide settings (mc_lookahead_enable,
+ *     mc_split_panel_enable) are atomic and read once per call.
  */
 #ifndef MC_H
 #define MC_H
@@ -124,6 +137,27 @@ mc_status mc_logdet(const void* A, int64_t n, int64_t lda, int dtype,
                     size_t work_bytes, void* stream);
 
 /*
+ * As mc_logdet, and also the pivot sequence: piv_col[s] is the ORIGINAL
+ * column index of the pivot chosen at step s (row s of A), s = 0..n-1 --
+ * the column of largest |a| in the condensed row s, ties to the smallest
+ * original index (Section 2.2; Figure 6 step 4.1).  The sequence is the
+ * same on the plain and the blocked paths (the plain path's slot moves of
+ * Section 2.4 and the blocked path's position exchanges only change where
+ * a column sits, not which original column a step takes).
+ *
+ * piv_col  device, n int32 (output; n = 0: may be NULL).  Written on
+ *          `stream`.  Meaningful when out->info == 0; after a singular or
+ *          non-finite result its entries from the failing step on are
+ *          unspecified.
+ * Other arguments as mc_logdet; argument numbers in error returns count
+ * piv_col as argument 7 (out is 8, work 9).
+ */
+mc_status mc_logdet_pivots(const void* A, int64_t n, int64_t lda, int dtype,
+                           int update, int64_t b, int32_t* piv_col,
+                           mc_result* out, void* work, size_t work_bytes,
+                           void* stream);
+
+/*
  * Factor call: the blocked condensation of mc_logdet run in place, keeping
  * the factors (the row-k factoring of Section 2.3 with the multipliers of
  * Figure 6 step 4.8 stored where they were eliminated).  On return A holds
@@ -149,19 +183,51 @@ mc_status mc_logdet_factor(void* A, int64_t n, int64_t lda, int dtype,
  * Backward call: gradA = g * A^{-T} = g * d log|det A| / dA from the output
  * of mc_logdet_factor (LU with row stride ld, perm).  A^{-1} = Q U^{-1}
  * L^{-1}: two blocked triangular substitutions whose off-diagonal updates
- * run on the matrix cores, then a permuted transpose.
+ * run on the matrix cores, then a permuted transpose.  (The paper computes
+ * only the forward value; the gradient is what the covariance workloads of
+ * its Abstract need to fit a model.)
  *
+ * LU, ld    device, row-major factors from mc_logdet_factor (read only).
+ * perm      device, n int32 from the same call.
+ * dtype     mc_dtype of LU and gradA.
  * grad_out  device pointer to one double g (the incoming gradient of
  *           log|det A|), or NULL for g = 1.
+ * fwd       device pointer to the factor call's mc_result, or NULL.  When
+ *           given and its info != 0 (singular, non-finite or aborted) the
+ *           factors are not a valid L U: every entry of gradA is NaN
+ *           (checked on the device; no host synchronisation).  When NULL the
+ *           factors must come from a call whose result had info == 0.
  * gradA     device, row-major n x n, row stride ldg (output).
- * work      >= mc_logdet_backward_workspace(n, dtype) bytes.
- * The factors must come from a call whose result had info == 0.
+ * work      >= mc_logdet_backward_workspace(n, dtype) bytes, 256-aligned.
  */
 size_t mc_logdet_backward_workspace(int64_t n, int dtype);
 mc_status mc_logdet_backward(const void* LU, int64_t n, int64_t ld,
                              const int32_t* perm, int dtype,
-                             const double* grad_out, void* gradA, int64_t ldg,
-                             void* work, size_t work_bytes, void* stream);
+                             const double* grad_out, const mc_result* fwd,
+                             void* gradA, int64_t ldg, void* work,
+                             size_t work_bytes, void* stream);
+
+/*
+ * Backward with the factors recomputed (for callers that did not keep
+ * them): factors a copy of A inside `work` exactly as mc_logdet_factor
+ * would (same b, update and pivots), then runs mc_logdet_backward on it
+ * with the forward result as `fwd`.  A is read only.
+ *
+ * out    device mc_result of the recomputed forward (optional; NULL: kept
+ *        inside the workspace).
+ * work   >= mc_logdet_backward_recompute_workspace(n, dtype, update, b)
+ *        bytes, 256-aligned: a copy of A, perm, the result, and one region
+ *        the factorisation and then the substitutions use.
+ * Other arguments as mc_logdet_factor and mc_logdet_backward.
+ */
+size_t mc_logdet_backward_recompute_workspace(int64_t n, int dtype,
+                                              int update, int64_t b);
+mc_status mc_logdet_backward_recompute(const void* A, int64_t n, int64_t lda,
+                                       int dtype, int update, int64_t b,
+                                       const double* grad_out, void* gradA,
+                                       int64_t ldg, mc_result* out,
+                                       void* work, size_t work_bytes,
+                                       void* stream);
 
 /*
  * Batched log-determinants of `batch` independent square matrices of
@@ -232,8 +298,9 @@ mc_status mc_autotune_batched(int dtype, int update, int64_t n_max_tune,
  * captured into a graph).  Other panels, and every panel with lookahead
  * off, run each kernel on the caller's stream.  Both schedules give the
  * same pivots and factors.  Returns the previous setting (1 on, 0 off).
- * Process-wide; calls that enqueue blocked work are serialised on a lock
- * while they do.  (Measured on MI355X at N = 8000, FP64: 24.7 ms on,
+ * Process-wide and atomic; a call reads it once, when it starts enqueuing
+ * (calls that enqueue blocked work are serialised on a lock while they
+ * do).  (Measured on MI355X at N = 8000, FP64: 24.7 ms on,
  * 33.2 ms off.)
  */
 int mc_lookahead_enable(int on);
@@ -247,8 +314,9 @@ int mc_lookahead_enable(int on);
  * multipliers per unit.  Off: the row-per-block panel kernels.  Both give
  * the same pivots and the same factors up to rounding order.  Off also
  * turns lookahead's second stream off (it only runs beside column-split
- * panels).  Returns the previous setting (1 on, 0 off).  Process-wide; not
- * synchronised with calls in flight.
+ * panels).  Returns the previous setting (1 on, 0 off).  Process-wide and
+ * atomic; a call reads it once, when it starts enqueuing, and keeps it for
+ * all of its panels.
  */
 int mc_split_panel_enable(int on);
 

@@ -37,7 +37,9 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_last_hip_error", "mc_logdet_factor_workspace",
            "mc_logdet_factor", "mc_logdet_backward_workspace",
            "mc_logdet_backward", "mc_lookahead_enable", "mc_default_panel",
-           "mc_split_panel_enable")
+           "mc_split_panel_enable", "mc_logdet_pivots",
+           "mc_logdet_backward_recompute_workspace",
+           "mc_logdet_backward_recompute")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -109,9 +111,16 @@ def lib() -> ctypes.CDLL:
     L.mc_logdet_factor.restype = ci
     L.mc_logdet_backward_workspace.argtypes = [i64, ci]
     L.mc_logdet_backward_workspace.restype = sz
-    L.mc_logdet_backward.argtypes = [vp, i64, i64, vp, ci, vp, vp, i64, vp, sz,
-                                     vp]
+    L.mc_logdet_backward.argtypes = [vp, i64, i64, vp, ci, vp, vp, vp, i64, vp,
+                                     sz, vp]
     L.mc_logdet_backward.restype = ci
+    L.mc_logdet_pivots.argtypes = [vp, i64, i64, ci, ci, i64, vp, vp, vp, sz, vp]
+    L.mc_logdet_pivots.restype = ci
+    L.mc_logdet_backward_recompute_workspace.argtypes = [i64, ci, ci, i64]
+    L.mc_logdet_backward_recompute_workspace.restype = sz
+    L.mc_logdet_backward_recompute.argtypes = [vp, i64, i64, ci, ci, i64, vp, vp,
+                                               i64, vp, vp, sz, vp]
+    L.mc_logdet_backward_recompute.restype = ci
     _lib = L
     return L
 
@@ -201,6 +210,22 @@ def slogdet(a: torch.Tensor, b: int = 0, update="native") -> Result:
     work = new_workspace(a.shape[0], a.device, a.dtype, update, b)
     logdet_async(a, result, work, b=b, update=update)
     return read_result(result)[0]
+
+
+def slogdet_pivots(a: torch.Tensor, b: int = 0, update="native"):
+    """(Result, piv_col): piv_col[s] is the original column of the pivot
+    taken at step s (an int32 device tensor of n entries).  Synchronises."""
+    n = a.shape[0]
+    lda = _square_rows(a)
+    result = new_result(a.device)
+    work = new_workspace(n, a.device, a.dtype, update, b)
+    piv = torch.full((max(n, 1),), -1, dtype=torch.int32, device=a.device)
+    st = lib().mc_logdet_pivots(a.data_ptr(), n, lda, _dtype_code(a),
+                                _update_code(update), b, piv.data_ptr(),
+                                result.data_ptr(), work.data_ptr(), work.numel(),
+                                _stream_ptr(None, a.device))
+    _check(st, "mc_logdet_pivots")
+    return read_result(result)[0], piv[:n]
 
 
 class Profile(NamedTuple):
@@ -418,8 +443,10 @@ def factor(a: torch.Tensor, b: int = -1, update="native"):
 
 
 def backward(lu: torch.Tensor, perm: torch.Tensor,
-             grad_out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """g * A^{-T} from factor()'s output; grad_out: device float64 scalar."""
+             grad_out: Optional[torch.Tensor] = None,
+             fwd: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g * A^{-T} from factor()'s output; grad_out: device float64 scalar;
+    fwd: the factor call's device result (NaN gradient when its info != 0)."""
     n = lu.shape[0]
     grad = torch.empty_like(lu)
     nb = lib().mc_logdet_backward_workspace(n, _dtype_code(lu))
@@ -429,10 +456,36 @@ def backward(lu: torch.Tensor, perm: torch.Tensor,
         grad_out = grad_out.detach().to(lu.device, torch.float64).contiguous()
         g_ptr = grad_out.data_ptr()
     st = lib().mc_logdet_backward(lu.data_ptr(), n, max(n, 1), perm.data_ptr(),
-                                  _dtype_code(lu), g_ptr, grad.data_ptr(),
-                                  max(n, 1), work.data_ptr(), work.numel(),
-                                  _stream_ptr(None, lu.device))
+                                  _dtype_code(lu), g_ptr,
+                                  fwd.data_ptr() if fwd is not None else None,
+                                  grad.data_ptr(), max(n, 1), work.data_ptr(),
+                                  work.numel(), _stream_ptr(None, lu.device))
     _check(st, "mc_logdet_backward")
+    return grad
+
+
+def backward_recompute(a: torch.Tensor, grad_out: Optional[torch.Tensor] = None,
+                       b: int = -1, update="native",
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g * A^{-T} with the factors recomputed from A inside the library's
+    workspace (mc_logdet_backward_recompute); out: optional device result."""
+    n = a.shape[0]
+    lda = _square_rows(a)
+    grad = torch.empty((n, n), dtype=a.dtype, device=a.device)
+    nb = lib().mc_logdet_backward_recompute_workspace(n, _dtype_code(a),
+                                                      _update_code(update), b)
+    if nb == 0 and n > 0:
+        raise MCError("unsupported combination for the recompute call")
+    work = torch.empty(max(nb, 1), dtype=torch.uint8, device=a.device)
+    g_ptr = None
+    if grad_out is not None:
+        grad_out = grad_out.detach().to(a.device, torch.float64).contiguous()
+        g_ptr = grad_out.data_ptr()
+    st = lib().mc_logdet_backward_recompute(
+        a.data_ptr(), n, lda, _dtype_code(a), _update_code(update), b, g_ptr,
+        grad.data_ptr(), max(n, 1), out.data_ptr() if out is not None else None,
+        work.data_ptr(), work.numel(), _stream_ptr(None, a.device))
+    _check(st, "mc_logdet_backward_recompute")
     return grad
 
 
@@ -440,14 +493,18 @@ class MCLogDet(torch.autograd.Function):
     """(sign, log|det A|) with d log|det A| / dA = A^{-T}.
 
     forward keeps the factors (L\\U and perm) when they fit `mem_budget`
-    bytes (None = always); otherwise backward recomputes them from A."""
+    bytes (None = always); otherwise backward recomputes them from A in the
+    library (mc_logdet_backward_recompute).  A failed factorisation
+    (singular, non-finite) gives logabsdet -inf or NaN in forward and an
+    all-NaN gradient in backward, decided on the device from the forward's
+    info (no host synchronisation)."""
 
     @staticmethod
     def forward(ctx, a, b=-1, update="native", mem_budget=None):
         lu, perm, res = factor(a, b=b, update=update)
         keep = mem_budget is None or lu.numel() * lu.element_size() <= mem_budget
         if keep:
-            ctx.save_for_backward(lu, perm)
+            ctx.save_for_backward(lu, perm, res)
         else:
             del lu, perm
             ctx.save_for_backward(a.detach())
@@ -461,11 +518,11 @@ class MCLogDet(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gsign, glogabs):
         if ctx.keep:
-            lu, perm = ctx.saved_tensors
+            lu, perm, res = ctx.saved_tensors
+            g = backward(lu, perm, glogabs, fwd=res)
         else:
             (a,) = ctx.saved_tensors
-            lu, perm, _ = factor(a, b=ctx.b, update=ctx.update)
-        g = backward(lu, perm, glogabs)
+            g = backward_recompute(a, glogabs, b=ctx.b, update=ctx.update)
         return g, None, None, None
 
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "mc.h"
@@ -32,6 +33,26 @@ hipError_t launch_write_result(mc_result* out, double logabsdet, double sign,
 {
     hipLaunchKernelGGL(write_result_kernel, dim3(1), dim3(1), 0, stream, out,
                        logabsdet, sign, info);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void copy_i32_kernel(int32_t* __restrict__ dst,
+                                const int* __restrict__ src, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+} // namespace
+
+hipError_t launch_copy_i32(int32_t* dst, const int* src, int64_t n,
+                           hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(copy_i32_kernel, dim3(blocks), dim3(256), 0, stream, dst,
+                       src, n);
     return hipGetLastError();
 }
 
@@ -128,6 +149,7 @@ PlainWork plain_carve(void* work, int64_t n)
     p += align_up(sizeof(int) * (size_t)n, kAlign);
     w.colid = reinterpret_cast<int*>(p);
     p += align_up(sizeof(int) * (size_t)n, kAlign);
+    w.piv_col = nullptr;
     w.state = reinterpret_cast<DevState*>(p);
     return w;
 }
@@ -230,13 +252,11 @@ extern "C" const char* mc_last_hip_error(void)
     return hipGetErrorString(g_last_hip);
 }
 
-static bool g_lookahead_on = true;
+static std::atomic<bool> g_lookahead_on{true};
 
 extern "C" int mc_lookahead_enable(int on)
 {
-    const int prev = g_lookahead_on ? 1 : 0;
-    g_lookahead_on = on != 0;
-    return prev;
+    return g_lookahead_on.exchange(on != 0) ? 1 : 0;
 }
 
 extern "C" int mc_split_panel_enable(int on) { return split_panel_set(on); }
@@ -663,14 +683,14 @@ extern "C" mc_status mc_logdet_factor(void* A, int64_t n, int64_t lda,
         w.ldw = lda;
         w.perm = perm;
         e = launch_blocked<double>(w.W, n, lda, b, update, w, out, st, true,
-                                   g_lookahead_on);
+                                   g_lookahead_on.load());
     } else {
         BlkWork<float> w = blocked_carve<float>(work, n, b, false);
         w.W = static_cast<float*>(A);
         w.ldw = lda;
         w.perm = perm;
         e = launch_blocked<float>(w.W, n, lda, b, update, w, out, st, true,
-                                  g_lookahead_on);
+                                  g_lookahead_on.load());
     }
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
@@ -686,23 +706,12 @@ extern "C" size_t mc_logdet_backward_workspace(int64_t n, int dtype)
            align_up(sizeof(DevState), kAlign);
 }
 
-extern "C" mc_status mc_logdet_backward(const void* LU, int64_t n, int64_t ld,
-                                        const int32_t* perm, int dtype,
-                                        const double* grad_out, void* gradA,
-                                        int64_t ldg, void* work,
-                                        size_t work_bytes, void* stream)
+static mc_status backward_impl(const void* LU, int64_t n, int64_t ld,
+                               const int32_t* perm, int dtype,
+                               const double* grad_out, const mc_result* fwd,
+                               void* gradA, int64_t ldg, void* work,
+                               hipStream_t st)
 {
-    if (n < 0 || n > kMaxN) return -2;
-    if (n > 0 && LU == nullptr) return -1;
-    if (ld < (n > 1 ? n : 1)) return -3;
-    if (n > 0 && perm == nullptr) return -4;
-    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -5;
-    if (n > 0 && gradA == nullptr) return -7;
-    if (ldg < (n > 1 ? n : 1)) return -8;
-    if (n == 0) return MC_OK;
-    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -9;
-    if (work_bytes < mc_logdet_backward_workspace(n, dtype)) return MC_ERR_WORKSPACE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
     const int64_t ldz = blocked_ldw(n, elem);
     char* p = static_cast<char*>(work);
@@ -714,23 +723,146 @@ extern "C" mc_status mc_logdet_backward(const void* LU, int64_t n, int64_t ld,
     hipError_t e;
     if (dtype == MC_DTYPE_F64)
         e = launch_backward<double>(static_cast<const double*>(LU), ld, perm, n,
-                                    grad_out, static_cast<double*>(gradA), ldg,
+                                    grad_out, fwd, static_cast<double*>(gradA), ldg,
                                     BwdWork<double>{static_cast<double*>(Z), ldz,
                                                     ident, state},
                                     st);
     else
         e = launch_backward<float>(static_cast<const float*>(LU), ld, perm, n,
-                                   grad_out, static_cast<float*>(gradA), ldg,
+                                   grad_out, fwd, static_cast<float*>(gradA), ldg,
                                    BwdWork<float>{static_cast<float*>(Z), ldz,
                                                   ident, state},
                                    st);
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
 
-extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
-                               int dtype, int update, int64_t b,
-                               mc_result* out, void* work, size_t work_bytes,
-                               void* stream)
+extern "C" mc_status mc_logdet_backward(const void* LU, int64_t n, int64_t ld,
+                                        const int32_t* perm, int dtype,
+                                        const double* grad_out,
+                                        const mc_result* fwd, void* gradA,
+                                        int64_t ldg, void* work,
+                                        size_t work_bytes, void* stream)
+{
+    if (n < 0 || n > kMaxN) return -2;
+    if (n > 0 && LU == nullptr) return -1;
+    if (ld < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && perm == nullptr) return -4;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -5;
+    if (n > 0 && gradA == nullptr) return -8;
+    if (ldg < (n > 1 ? n : 1)) return -9;
+    if (n == 0) return MC_OK;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -10;
+    if (work_bytes < mc_logdet_backward_workspace(n, dtype)) return MC_ERR_WORKSPACE;
+    return backward_impl(LU, n, ld, perm, dtype, grad_out, fwd, gradA, ldg, work,
+                         static_cast<hipStream_t>(stream));
+}
+
+// ---- backward with the factors recomputed: a copy of A is factored in the
+// workspace, then the backward runs on it.  Layout: LU (n x ldw), perm,
+// the forward result, then one region shared by the factor call's
+// workspace and the backward's (the second starts after the first ends on
+// the stream).
+namespace {
+
+template <typename T>
+__global__ void copy_matrix_kernel(const T* __restrict__ A, int64_t lda,
+                                   T* __restrict__ B, int64_t ldb, int64_t n)
+{
+    const int64_t i = blockIdx.x;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) B[i * ldb + j] = A[i * lda + j];
+}
+
+struct RecomputeLayout {
+    size_t lu, perm, res, region, total;
+    int64_t ldw;
+};
+
+RecomputeLayout recompute_layout(int64_t n, int dtype, int64_t b)
+{
+    const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
+    RecomputeLayout L;
+    L.ldw = blocked_ldw(n, elem);
+    L.lu = 0;
+    L.perm = L.lu + align_up(elem * (size_t)n * (size_t)L.ldw, kAlign);
+    L.res = L.perm + align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1), kAlign);
+    L.region = L.res + align_up(sizeof(mc_result), kAlign);
+    L.total = L.region + std::max(blocked_bytes(n, dtype, b, false),
+                                  mc_logdet_backward_workspace(n, dtype));
+    return L;
+}
+
+} // namespace
+
+extern "C" size_t mc_logdet_backward_recompute_workspace(int64_t n, int dtype,
+                                                         int update, int64_t b)
+{
+    if (n < 0 || n > kMaxN) return 0;
+    if (b < 0) b = default_panel(n, dtype);
+    if (!blocked_supported(dtype, update, b)) return 0;
+    return recompute_layout(n, dtype, b).total;
+}
+
+extern "C" mc_status mc_logdet_backward_recompute(
+    const void* A, int64_t n, int64_t lda, int dtype, int update, int64_t b,
+    const double* grad_out, void* gradA, int64_t ldg, mc_result* out,
+    void* work, size_t work_bytes, void* stream)
+{
+    if (n < 0 || n > kMaxN) return -2;
+    if (n > 0 && A == nullptr) return -1;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -4;
+    if (update < MC_UPDATE_NATIVE || update > MC_UPDATE_BF16X3) return -5;
+    if (b < 0) b = default_panel(n, dtype);
+    if (!blocked_supported(dtype, update, b)) return MC_ERR_UNSUPPORTED;
+    if (n > 0 && gradA == nullptr) return -8;
+    if (ldg < (n > 1 ? n : 1)) return -9;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0)
+        return out == nullptr || launch_write_result(out, 0.0, 1.0, 0, st) == hipSuccess
+                   ? MC_OK
+                   : MC_ERR_HIP;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -11;
+    const RecomputeLayout L = recompute_layout(n, dtype, b);
+    if (work_bytes < L.total) return MC_ERR_WORKSPACE;
+    char* base = static_cast<char*>(work);
+    int32_t* perm = reinterpret_cast<int32_t*>(base + L.perm);
+    mc_result* res = out ? out : reinterpret_cast<mc_result*>(base + L.res);
+    void* region = base + L.region;
+    hipError_t e;
+    if (dtype == MC_DTYPE_F64) {
+        double* LU = reinterpret_cast<double*>(base + L.lu);
+        hipLaunchKernelGGL(copy_matrix_kernel<double>, dim3((unsigned)n), dim3(256), 0, st,
+                           static_cast<const double*>(A), lda, LU, L.ldw, n);
+        BlkWork<double> w = blocked_carve<double>(region, n, b, false);
+        w.W = LU;
+        w.ldw = L.ldw;
+        w.perm = perm;
+        e = launch_blocked<double>(LU, n, L.ldw, b, update, w, res, st, true,
+                                   g_lookahead_on.load());
+        if (e == hipSuccess)
+            return backward_impl(LU, n, L.ldw, perm, dtype, grad_out, res, gradA, ldg,
+                                 region, st);
+    } else {
+        float* LU = reinterpret_cast<float*>(base + L.lu);
+        hipLaunchKernelGGL(copy_matrix_kernel<float>, dim3((unsigned)n), dim3(256), 0, st,
+                           static_cast<const float*>(A), lda, LU, L.ldw, n);
+        BlkWork<float> w = blocked_carve<float>(region, n, b, false);
+        w.W = LU;
+        w.ldw = L.ldw;
+        w.perm = perm;
+        e = launch_blocked<float>(LU, n, L.ldw, b, update, w, res, st, true,
+                                  g_lookahead_on.load());
+        if (e == hipSuccess)
+            return backward_impl(LU, n, L.ldw, perm, dtype, grad_out, res, gradA, ldg,
+                                 region, st);
+    }
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
+}
+
+static mc_status logdet_impl(const void* A, int64_t n, int64_t lda, int dtype,
+                             int update, int64_t b, int32_t* piv_col,
+                             mc_result* out, void* work, size_t work_bytes,
+                             void* stream)
 {
     if (n < 0 || n > kMaxN) return -2;
     if (n > 0 && A == nullptr) return -1;
@@ -752,20 +884,48 @@ extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
     hipError_t e;
     if (plain) {
         if (work_bytes < plain_workspace_bytes(n)) return MC_ERR_WORKSPACE;
-        const PlainWork w = plain_carve(work, n);
+        PlainWork w = plain_carve(work, n);
+        w.piv_col = piv_col;
         e = launch_plain_f64(static_cast<const double*>(A), n, lda, w, out, st);
     } else {
         if (work_bytes < blocked_workspace_bytes(n, dtype, b))
             return MC_ERR_WORKSPACE;
-        if (dtype == MC_DTYPE_F64)
+        if (dtype == MC_DTYPE_F64) {
+            const BlkWork<double> w = blocked_carve<double>(work, n, b);
             e = launch_blocked<double>(static_cast<const double*>(A), n, lda,
-                                       b, update,
-                                       blocked_carve<double>(work, n, b), out,
-                                       st, false, g_lookahead_on);
-        else
+                                       b, update, w, out, st, false,
+                                       g_lookahead_on.load());
+            // after the last panel, position s holds the column step s took
+            if (e == hipSuccess && piv_col) e = launch_copy_i32(piv_col, w.perm, n, st);
+        } else {
+            const BlkWork<float> w = blocked_carve<float>(work, n, b);
             e = launch_blocked<float>(static_cast<const float*>(A), n, lda, b,
-                                      update, blocked_carve<float>(work, n, b),
-                                      out, st, false, g_lookahead_on);
+                                      update, w, out, st, false,
+                                      g_lookahead_on.load());
+            if (e == hipSuccess && piv_col) e = launch_copy_i32(piv_col, w.perm, n, st);
+        }
     }
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
+}
+
+extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
+                               int dtype, int update, int64_t b,
+                               mc_result* out, void* work, size_t work_bytes,
+                               void* stream)
+{
+    return logdet_impl(A, n, lda, dtype, update, b, nullptr, out, work,
+                       work_bytes, stream);
+}
+
+extern "C" mc_status mc_logdet_pivots(const void* A, int64_t n, int64_t lda,
+                                      int dtype, int update, int64_t b,
+                                      int32_t* piv_col, mc_result* out,
+                                      void* work, size_t work_bytes,
+                                      void* stream)
+{
+    if (n > 0 && piv_col == nullptr) return -7;
+    const mc_status s = logdet_impl(A, n, lda, dtype, update, b, piv_col, out,
+                                    work, work_bytes, stream);
+    // logdet_impl numbers `out` as argument 7; here it is argument 8
+    return s == -7 ? -8 : (s == -8 ? -9 : s);
 }

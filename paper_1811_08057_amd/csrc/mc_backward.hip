@@ -98,16 +98,21 @@ bwd_usolve_diag(const T* __restrict__ LU, int64_t ld, T* Z, int64_t ldz,
         if (r < nb) Z[(I0 + r) * ldz + j] = z[r];
 }
 
-// G[j][perm[s]] = g * Z[s][j], 32 x 32 tiles through LDS.
+// G[j][perm[s]] = g * Z[s][j], 32 x 32 tiles through LDS.  When the
+// forward result `fwd` (optional) reports a failed factorisation (info != 0:
+// singular, non-finite or aborted) the factors are not a valid L U, and every
+// entry of G is NaN instead.
 template <typename T>
 __global__ void __launch_bounds__(kBwdThreads)
 bwd_output(const T* __restrict__ Z, int64_t ldz, const int* __restrict__ perm,
-           int64_t n, const double* grad_out, T* G, int64_t ldg)
+           int64_t n, const double* grad_out, const mc_result* fwd, T* G,
+           int64_t ldg)
 {
     __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5; // 32 x 8
     const int64_t s0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
-    const T g = grad_out ? (T)(*grad_out) : T(1);
+    T g = grad_out ? (T)(*grad_out) : T(1);
+    if (fwd && fwd->info != 0) g = (T)NAN;
     for (int y = ty; y < 32; y += 8) {
         const int64_t s = s0 + y, j = j0 + tx;
         tile[y][tx] = (s < n && j < n) ? Z[s * ldz + j] : T(0);
@@ -115,7 +120,11 @@ bwd_output(const T* __restrict__ Z, int64_t ldz, const int* __restrict__ perm,
     __syncthreads();
     for (int y = ty; y < 32; y += 8) {
         const int64_t j = j0 + y, s = s0 + tx;
-        if (j < n && s < n) G[j * ldg + perm[s]] = g * tile[tx][y];
+        if (j < n && s < n) {
+            // perm is read only from a valid factorisation
+            const int64_t c = (fwd && fwd->info != 0) ? s : perm[s];
+            G[j * ldg + c] = g * tile[tx][y];
+        }
     }
 }
 
@@ -143,8 +152,8 @@ static void launch_diag(bool lower, const T* LU, int64_t ld, T* Z, int64_t ldz,
 
 template <typename T>
 hipError_t launch_backward(const T* LU, int64_t ld, const int* perm, int64_t n,
-                           const double* grad_out, T* G, int64_t ldg,
-                           BwdWork<T> w, hipStream_t st)
+                           const double* grad_out, const mc_result* fwd, T* G,
+                           int64_t ldg, BwdWork<T> w, hipStream_t st)
 {
     const int update = MC_UPDATE_NATIVE;
     hipLaunchKernelGGL(bwd_init<T>, dim3((unsigned)n), dim3(kBwdThreads), 0, st,
@@ -184,16 +193,17 @@ hipError_t launch_backward(const T* LU, int64_t ld, const int* perm, int64_t n,
     }
     const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32));
     hipLaunchKernelGGL(bwd_output<T>, grid, dim3(kBwdThreads), 0, st, w.Z, w.ldz,
-                       perm, n, grad_out, G, ldg);
+                       perm, n, grad_out, fwd, G, ldg);
     return hipGetLastError();
 }
 
 template hipError_t launch_backward<double>(const double*, int64_t, const int*,
-                                            int64_t, const double*, double*,
-                                            int64_t, BwdWork<double>,
-                                            hipStream_t);
+                                            int64_t, const double*,
+                                            const mc_result*, double*, int64_t,
+                                            BwdWork<double>, hipStream_t);
 template hipError_t launch_backward<float>(const float*, int64_t, const int*,
-                                           int64_t, const double*, float*,
-                                           int64_t, BwdWork<float>, hipStream_t);
+                                           int64_t, const double*,
+                                           const mc_result*, float*, int64_t,
+                                           BwdWork<float>, hipStream_t);
 
 } // namespace mc

@@ -29,6 +29,7 @@
 //   gemm       A22 <- gather(A22) - L21 * U12    (mc_gemm.hip)
 #include <algorithm>
 #include <type_traits>
+#include <atomic>
 #include <mutex>
 
 #include "mc_device.h"
@@ -982,14 +983,9 @@ constexpr int kSplitThreads = 512;
 constexpr int kSplitWaves = kSplitThreads / kWave;
 constexpr int kSplitNone = 0x7fffffff; // a column no step of the panel took
 
-static bool g_split_on = true;
+static std::atomic<bool> g_split_on{true};
 
-int split_panel_set(int on)
-{
-    const int prev = g_split_on ? 1 : 0;
-    g_split_on = on != 0;
-    return prev;
-}
+int split_panel_set(int on) { return g_split_on.exchange(on != 0) ? 1 : 0; }
 
 // Largest |a| first, then the smaller key (original id in the high word).
 __device__ __forceinline__ void split_take(uint64_t& a, uint64_t& k, uint64_t oa,
@@ -1634,7 +1630,7 @@ template <typename T, int CPW>
 static hipError_t launch_split(int64_t n, int64_t s0, int nb, const BlkWork<T>& w,
                                hipStream_t stream, bool on_xcc0)
 {
-    static bool attr_set = false;
+    static bool attr_set = false; // guarded by g_sched_mu (held by the caller)
     if (!attr_set) {
         const hipError_t e = hipFuncSetAttribute(
             reinterpret_cast<const void*>(&blk_panel_split<T, CPW>),
@@ -1651,9 +1647,10 @@ static hipError_t launch_split(int64_t n, int64_t s0, int nb, const BlkWork<T>& 
     return hipSuccess;
 }
 
-static bool split_fits(int64_t width)
+// `on`: the column-split setting, read once per call.
+static bool split_fits(int64_t width, bool on)
 {
-    return g_split_on && width <= (int64_t)kSplitSlices * kSplitWaves * 32;
+    return on && width <= (int64_t)kSplitSlices * kSplitWaves * 32;
 }
 
 // The column-split panel for a panel of width n - s0 (split_fits): the
@@ -2118,7 +2115,7 @@ static size_t trsm_mfma_lds_bytes(int nb)
                         (size_t)(ntri + nblk) * 256);
 }
 
-// ---- one-panel lookahead ----
+// ---- per-device scheduling: one-panel lookahead, and calls one at a time ----
 //
 // The next panel only needs its own rows brought up to date, so the
 // trailing update is split: the next panel's rows on the caller's stream,
@@ -2129,39 +2126,51 @@ static size_t trsm_mfma_lds_bytes(int nb)
 // caller's stream waits for the join before the next triangular solve and
 // before returning.  One side stream and event pair per device, reused
 // under a lock held while a call enqueues its work.
-struct Lookahead {
+//
+// A column-split panel needs all of its slices resident together on one
+// XCD.  Two blocked calls running at once on one device (from different
+// streams) would contend for those compute units, so the device's blocked
+// calls run one after another on the GPU: each call's first kernel waits
+// for an event the previous call recorded after its last kernel.  Calls
+// enqueued under graph capture neither wait nor record (the graph is not
+// executed then); replaying such a graph beside another blocked call on the
+// same device is the caller's to order.
+struct DevSched {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t done = nullptr; // after the device's last blocked call
+    bool done_recorded = false;
     bool ready = false, failed = false;
     bool all_xccs = false; // the device exposes its eight XCDs (ids 0..7)
 };
 
 constexpr int kMaxDevices = 64;
-static Lookahead g_lookahead[kMaxDevices];
-static std::mutex g_lookahead_mu;
+static DevSched g_sched[kMaxDevices];
+static std::mutex g_sched_mu; // guards g_sched and every enqueue of a blocked call
 
-// The device's lookahead resources, created on first use; nullptr when
-// they cannot be created (the update then runs on one stream).
-static Lookahead* lookahead_get()
+// The current device's scheduling state, created on first use; nullptr
+// when it cannot be created.  Caller holds g_sched_mu.
+static DevSched* sched_get()
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-    Lookahead& la = g_lookahead[dev];
-    if (!la.ready && !la.failed) {
-        if (hipStreamCreateWithFlags(&la.side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&la.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&la.join, hipEventDisableTiming) != hipSuccess) {
-            la.failed = true;
+    DevSched& d = g_sched[dev];
+    if (!d.ready && !d.failed) {
+        if (hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&d.join, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&d.done, hipEventDisableTiming) != hipSuccess) {
+            d.failed = true;
             (void)hipGetLastError();
             return nullptr;
         }
         int xccs = 0;
-        la.all_xccs = hipDeviceGetAttribute(&xccs, hipDeviceAttributeNumberOfXccs, dev) ==
-                          hipSuccess && xccs == 8;
+        d.all_xccs = hipDeviceGetAttribute(&xccs, hipDeviceAttributeNumberOfXccs, dev) ==
+                         hipSuccess && xccs == 8;
         (void)hipGetLastError();
-        la.ready = true;
+        d.ready = true;
     }
-    return la.ready ? &la : nullptr;
+    return d.ready ? &d : nullptr;
 }
 
 // The panel-k view of the workspace: alternate column-map sets.
@@ -2210,9 +2219,11 @@ static hipError_t trailing(const BlkWork<T>& w, int update, int64_t s0, int nb,
 template <typename T>
 hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                           int update, BlkWork<T> w, mc_result* out,
-                          hipStream_t stream, bool factor, bool lookahead)
+                          hipStream_t stream, bool factor, bool lookahead,
+                          bool serialize)
 {
-    static bool attr_set = false;
+    std::unique_lock<std::mutex> lock(g_sched_mu);
+    static bool attr_set = false; // guarded by g_sched_mu
     if (!attr_set && trsm_mfma_lds_bytes<T>((int)kMaxPanel) > 64 * 1024) {
         for (const void* f : {reinterpret_cast<const void*>(&blk_trsm_mfma<T, false>),
                               reinterpret_cast<const void*>(&blk_trsm_mfma<T, true>)}) {
@@ -2223,10 +2234,28 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         }
         attr_set = true;
     }
+    // serialize = false: no per-device state at all (no side stream, no
+    // events, no ordering against other calls) -- for callers that must not
+    // have the library create runtime objects; lookahead is then off too.
+    DevSched* ds = nullptr;
+    if (serialize || lookahead) {
+        ds = sched_get();
+        if (ds == nullptr) return note_hip_error(hipErrorOutOfMemory);
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (ds) {
+        const hipError_t e = hipStreamIsCapturing(stream, &cap);
+        if (e != hipSuccess) return note_hip_error(e);
+    }
+    const bool ordered = ds != nullptr && serialize && cap == hipStreamCaptureStatusNone;
+    if (ordered && ds->done_recorded) { // the device's previous blocked call
+        const hipError_t e = hipStreamWaitEvent(stream, ds->done, 0);
+        if (e != hipSuccess) return note_hip_error(e);
+    }
+    const bool split_on = g_split_on.load();
     hipLaunchKernelGGL(blk_init<T>, dim3((unsigned)n), dim3(kBlkThreads), 0,
                        stream, A, lda, n, w);
-    std::unique_lock<std::mutex> lock(g_lookahead_mu);
-    Lookahead* la = lookahead ? lookahead_get() : nullptr;
+    DevSched* la = lookahead ? ds : nullptr;
     bool pending = false; // side-stream work the caller's stream must join
     bool beside = false;  // ... and it leaves XCD 0 to the next panel
     for (int64_t s0 = 0, k = 0; s0 < n; s0 += b, ++k) {
@@ -2235,7 +2264,7 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         // the panel chains need their blocks resident together on one XCD:
         // the one block 0 lands on, or XCD 0 when the trailing update
         // running beside the panel (lookahead) leaves that XCD alone
-        const bool split = split_fits(n - s0);
+        const bool split = split_fits(n - s0, split_on);
         if (!split) launch_head<T>(n, s0, w, stream);
         const int ept = step_ept(n - s0);
         const bool persistent = !split && ept > 0 && nb > 1;
@@ -2299,7 +2328,7 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         // panel's TRSM or blk_perm).  Otherwise one launch for all rows:
         // beside a row-per-block panel chain the update's tiles would share
         // its XCD and slow it more than the overlap gains.
-        beside = la && la->all_xccs && split_fits(n - pend) && rows > b;
+        beside = la && la->all_xccs && split_fits(n - pend, split_on) && rows > b;
         const int64_t next = beside ? b : rows;
         hipError_t e = trailing(wk, update, s0, nb, pend, next, n, stream, nullptr);
         if (e != hipSuccess) return e;
@@ -2345,14 +2374,25 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     }
     hipLaunchKernelGGL(blk_finalize, dim3(1), dim3(kBlkThreads), 0, stream, n,
                        w.piv_pos, w.piv_val, w.state, out);
-    return hipGetLastError();
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (ordered) {
+        const hipError_t e = hipEventRecord(ds->done, stream);
+        if (e != hipSuccess) return note_hip_error(e);
+        ds->done_recorded = true;
+    }
+    return hipSuccess;
 }
 
 template hipError_t launch_blocked<double>(const double*, int64_t, int64_t,
                                            int64_t, int, BlkWork<double>,
-                                           mc_result*, hipStream_t, bool, bool);
+                                           mc_result*, hipStream_t, bool, bool,
+                                           bool);
 template hipError_t launch_blocked<float>(const float*, int64_t, int64_t,
                                           int64_t, int, BlkWork<float>,
-                                          mc_result*, hipStream_t, bool, bool);
+                                          mc_result*, hipStream_t, bool, bool,
+                                          bool);
 
 } // namespace mc

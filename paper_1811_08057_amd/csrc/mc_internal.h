@@ -27,6 +27,8 @@ struct PlainWork {
     double* piv_val; // pivot of each step
     int* piv_slot;   // slot of each step's pivot in its row
     int* colid;      // original column held by each slot
+    int* piv_col;    // optional (caller's, may be null): original column of
+                     // each step's pivot
     DevState* state;
 };
 
@@ -73,7 +75,8 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b,
 template <typename T>
 hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                           int update, BlkWork<T> w, mc_result* out,
-                          hipStream_t stream, bool factor, bool lookahead);
+                          hipStream_t stream, bool factor, bool lookahead,
+                          bool serialize = true);
 
 // Column-split panel kernel on (default) or off; returns the previous setting.
 int split_panel_set(int on);
@@ -82,6 +85,11 @@ size_t plain_workspace_bytes(int64_t n);
 PlainWork plain_carve(void* work, int64_t n);
 hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
                             PlainWork w, mc_result* out, hipStream_t stream);
+
+// Copy n int32 values on the stream (a kernel, so that graph capture
+// records no memory-copy or memset node).
+hipError_t launch_copy_i32(int32_t* dst, const int* src, int64_t n,
+                           hipStream_t stream);
 
 hipError_t launch_write_result(mc_result* out, double logabsdet, double sign,
                                int64_t info, hipStream_t stream);
@@ -111,8 +119,8 @@ struct BwdWork {
 
 template <typename T>
 hipError_t launch_backward(const T* LU, int64_t ld, const int* perm, int64_t n,
-                           const double* grad_out, T* G, int64_t ldg,
-                           BwdWork<T> w, hipStream_t st);
+                           const double* grad_out, const mc_result* fwd, T* G,
+                           int64_t ldg, BwdWork<T> w, hipStream_t st);
 
 // Remember a failing HIP status for mc_last_hip_error(); returns it.
 hipError_t note_hip_error(hipError_t e);

@@ -52,6 +52,7 @@ plain_init(const double* __restrict__ A, int64_t n, PlainWork w)
         w.state->bad_step = 0;
         w.piv_val[0] = k.value;
         w.piv_slot[0] = k.slot;
+        if (w.piv_col) w.piv_col[0] = k.colid;
         shp = k.value;
         shflag = st;
     }
@@ -107,6 +108,7 @@ plain_step(const double* src, int64_t lds, int64_t n, int64_t s,
                 st = kStatusSingular;
             w.piv_val[s + 1] = k.value;
             w.piv_slot[s + 1] = k.slot;
+            if (w.piv_col) w.piv_col[s + 1] = k.colid;
             if (st != kStatusOk) {
                 w.state->bad_step = (int)(s + 1);
                 w.state->status = st;

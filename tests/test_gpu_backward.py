@@ -133,3 +133,55 @@ def test_factor_singular_reports_info():
     r = mc.read_result(res)[0]
     ref = O.slogdet(a)
     assert (r.sign, r.info) == (ref.sign, ref.info) and r.logabsdet == -math.inf
+
+
+def test_backward_after_failed_forward_is_nan():
+    """A singular or non-finite input: the forward reports it (info != 0)
+    and the backward, given the forward's result, returns an all-NaN
+    gradient instead of one built from invalid factors -- decided on the
+    device (no host synchronisation in MCLogDet)."""
+    a = synth.uniform(150, 4)
+    z = a.copy()
+    z[40] = 0.0
+    nf = a.copy()
+    nf[3, 7] = np.nan
+    for m, info in ((z, 41), (nf, mc.INFO_NONFINITE)):
+        x = dev(m).requires_grad_(True)
+        sign, logabs = mc.slogdet_autograd(x, b=32)
+        assert float(sign) == 0.0
+        logabs.backward()
+        assert torch.isnan(x.grad).all()
+        lu, perm, res = mc.factor(dev(m), b=32)
+        assert mc.read_result(res)[0].info == info
+        g = mc.backward(lu, perm, fwd=res)
+        assert torch.isnan(g).all()
+    # a good factorisation with fwd given: an ordinary gradient
+    lu, perm, res = mc.factor(dev(a), b=32)
+    g = mc.backward(lu, perm, fwd=res).cpu().numpy()
+    assert rel_fro(g, O.grad_logabsdet(a)) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_backward_recompute_matches_kept_factors(dtype):
+    """mc_logdet_backward_recompute (factors rebuilt inside the library)
+    against the backward on kept factors and the oracle's inverse; the
+    autograd function takes that route under a memory budget."""
+    n = 700
+    a = synth.wishart(n, 71)
+    x = dev(a, dtype)
+    lu, perm, res = mc.factor(x, b=64)
+    kept = mc.backward(lu, perm, fwd=res)
+    out = mc.new_result(DEV)
+    again = mc.backward_recompute(x, b=64, out=out)
+    r = mc.read_result(out)[0]
+    ref_r = mc.read_result(res)[0]
+    assert r == ref_r
+    # the same kernels on the same input: bitwise
+    assert torch.equal(kept, again)
+    tol = 1e-10 if dtype == torch.float64 else 1e-4
+    a_in = a if dtype == torch.float64 else a.astype(np.float32).astype(np.float64)
+    assert rel_fro(again.double().cpu().numpy(), O.grad_logabsdet(a_in)) <= tol
+    y = x.clone().requires_grad_(True)
+    _, logabs = mc.slogdet_autograd(y, b=64, mem_budget=0)
+    logabs.backward()
+    assert torch.equal(y.grad, kept)

@@ -36,7 +36,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 @pytest.fixture(scope="module")
 def batch64():
     """Sizes and FP64 matrices: the stored values' draws, with each X^T X
-    formed on the GPU in FP64 (rounding-level differences only)."""
+    formed on the GPU in FP64 (exact on the draws' 2^-12 grid), hashing to
+    the bytes the stored values were computed on."""
     def gram(x):
         xd = torch.from_numpy(x).to(DEV)
         return torch.matmul(xd.t().contiguous(), xd).cpu().numpy()
@@ -46,6 +47,8 @@ def batch64():
     with open(os.path.join(GOLDEN, "expected_wishart_batch64.json")) as f:
         exp = json.load(f)
     assert sizes == exp["sizes"]
+    assert synth.sha256_of(mats) == exp["sha256_f64"]
+    assert synth.sha256_of([m.astype(np.float32) for m in mats]) == exp["sha256_f32"]
     return sizes, mats, exp
 
 
@@ -143,3 +146,29 @@ def test_batch64_backward_f32(batch64):
         err = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
         print(f"[batch64] f32 member {i} n={sizes[i]}: rel Frobenius {err:.3e}")
         assert err <= 1e-3
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch64_backward_sampled_entries_every_member(batch64, precision):
+    """Every member, both precisions: 16 seeded entries of the gradient
+    (including the two diagonal corners) against A^{-T} from the oracle's
+    Gauss-Jordan inverse, stored by tests/golden/make_expected.py (FP32:
+    the inverse of the FP32-rounded input).  Bar per entry: 1e-10 (FP64)
+    or 1e-4 (FP32) times the largest |sampled entry| of that member."""
+    sizes, mats, exp = batch64
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    tol = 1e-10 if precision == "f64" else 1e-4
+    worst = 0.0
+    print(f"[batch64] sampled gradient entries {precision}", flush=True)
+    for k, (m, smp) in enumerate(zip(mats, exp["grad_samples"])):
+        a = torch.from_numpy(m).to(DEV, dtype).requires_grad_(True)
+        _, logabs = mc.slogdet_autograd(a)
+        logabs.backward()
+        g = a.grad.double().cpu().numpy()
+        ref = np.array(smp[precision])
+        got = np.array([g[i, j] for i, j in smp["ij"]])
+        scale = np.abs(ref).max()
+        err = float(np.abs(got - ref).max() / scale)
+        worst = max(worst, err)
+        assert err <= tol, (k, sizes[k], err)
+    print(f"[batch64] {precision}: worst sampled-entry error {worst:.3e}")

@@ -129,7 +129,11 @@ def test_batched_wishart_batch512_expected(precision):
         exp = json.load(f)
     sizes, mats = synth.make("wishart_batch512")
     assert sizes == exp["sizes"]
+    # the bytes the oracle values were computed on (exact Gram products)
+    assert synth.sha256_of(mats) == exp["sha256_f64"]
     dtype = torch.float64 if precision == "f64" else torch.float32
+    if precision == "f32":
+        assert synth.sha256_of([m.astype(np.float32) for m in mats]) == exp["sha256_f32"]
     tol = 1e-9 if precision == "f64" else 1e-5
     print(f"[batched] wishart_batch512 {precision}", flush=True)
     for update in (["native"] if precision == "f64" else ["f32", "bf16x3"]):

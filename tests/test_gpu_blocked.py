@@ -303,10 +303,10 @@ def _graph_replays():
 
 @pytest.fixture(scope="module")
 def wishart_n16384():
-    """The N = 16384 Wishart workload (seed 3): the same draws as the
-    stored oracle values, with X^T X formed on the GPU in FP64 (it differs
-    from the host product by rounding, which moves log|det| by ~1e-12
-    relative)."""
+    """The N = 16384 Wishart workload (seed 3).  Its draws lie on a 2^-12
+    grid, so X^T X is exact and the same bytes on any device; it is formed
+    on the GPU in FP64 here and must hash to the bytes the stored oracle
+    values were computed on."""
     def gram(x):
         xd = torch.from_numpy(x).to(DEV)
         g = torch.matmul(xd.t().contiguous(), xd).cpu().numpy()
@@ -315,7 +315,12 @@ def wishart_n16384():
         return g
 
     print("[blocked] generating wishart_n16384", flush=True)
-    return synth.make("wishart_n16384", gram=gram)
+    a = synth.make("wishart_n16384", gram=gram)
+    with open(os.path.join(GOLDEN, "expected_wishart_n16384.json")) as f:
+        exp = json.load(f)
+    assert synth.sha256_of(a) == exp["sha256_f64"]
+    assert synth.sha256_of(a.astype(np.float32)) == exp["sha256_f32"]
+    return a
 
 
 @pytest.mark.parametrize("precision,update", [("f64", "native"),
