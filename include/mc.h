@@ -158,6 +158,39 @@ mc_status mc_logdet_pivots(const void* A, int64_t n, int64_t lda, int dtype,
                            void* stream);
 
 /*
+ * Pivot-column rules inside the pivot row.  The paper's rule is the column
+ * of largest |a_kl| (Section 2.2).  Section 1 describes two earlier rules
+ * that the paper argues against (Section 2.2: a tiny pivot can lose digits
+ * or overflow the running product): the first non-zero entry of the row
+ * (Beliakov) and the non-zero entry whose |a| is closest to 1 (Haque).
+ * Ties go to the smallest original column under every rule.
+ */
+#define MC_PIVOT_MAXABS 0
+#define MC_PIVOT_FIRST_NONZERO 1
+#define MC_PIVOT_CLOSEST_TO_ONE 2
+
+/*
+ * The plain (unblocked) FP64 condensation of mc_logdet with b = 0 under a
+ * chosen pivot-column rule (MC_PIVOT_*), for studying the rules' accuracy;
+ * MC_PIVOT_MAXABS is exactly mc_logdet_pivots with b = 0.  Under the other
+ * two rules a row with no non-zero entry is singular as before; otherwise
+ * the step takes the rule's choice however small it is.
+ *
+ * A        device, row-major n x n FP64, row stride lda; read only.
+ * rule     MC_PIVOT_MAXABS, MC_PIVOT_FIRST_NONZERO or MC_PIVOT_CLOSEST_TO_ONE.
+ * piv_col  device, n int32 (output), or NULL: the original column of each
+ *          step's pivot, as in mc_logdet_pivots.
+ * out      device mc_result.
+ * work     >= mc_logdet_workspace(n, MC_DTYPE_F64, MC_UPDATE_NATIVE, 0)
+ *          bytes, 256-byte aligned.
+ * Error returns number the arguments A = 1, n = 2, lda = 3, rule = 4,
+ * out = 6, work = 7.
+ */
+mc_status mc_logdet_rule(const void* A, int64_t n, int64_t lda, int rule,
+                         int32_t* piv_col, mc_result* out, void* work,
+                         size_t work_bytes, void* stream);
+
+/*
  * Factor call: the blocked condensation of mc_logdet run in place, keeping
  * the factors (the row-k factoring of Section 2.3 with the multipliers of
  * Figure 6 step 4.8 stored where they were eliminated).  On return A holds

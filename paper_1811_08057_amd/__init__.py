@@ -25,6 +25,9 @@ LIB_PATH = os.path.join(_HERE, "libmc.so")
 DTYPE_F64, DTYPE_F32 = 0, 1
 UPDATE_NATIVE, UPDATE_F32, UPDATE_BF16X3 = 0, 1, 2
 INFO_NONFINITE = -1
+PIVOT_MAXABS, PIVOT_FIRST_NONZERO, PIVOT_CLOSEST_TO_ONE = 0, 1, 2
+_RULES = {"maxabs": PIVOT_MAXABS, "first_nonzero": PIVOT_FIRST_NONZERO,
+          "closest_to_one": PIVOT_CLOSEST_TO_ONE}
 
 _UPDATES = {"native": UPDATE_NATIVE, "f32": UPDATE_F32,
             "bf16x3": UPDATE_BF16X3}
@@ -39,7 +42,7 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_logdet_backward", "mc_lookahead_enable", "mc_default_panel",
            "mc_split_panel_enable", "mc_logdet_pivots",
            "mc_logdet_backward_recompute_workspace",
-           "mc_logdet_backward_recompute")
+           "mc_logdet_backward_recompute", "mc_logdet_rule")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -121,6 +124,8 @@ def lib() -> ctypes.CDLL:
     L.mc_logdet_backward_recompute.argtypes = [vp, i64, i64, ci, ci, i64, vp, vp,
                                                i64, vp, vp, sz, vp]
     L.mc_logdet_backward_recompute.restype = ci
+    L.mc_logdet_rule.argtypes = [vp, i64, i64, ci, vp, vp, vp, sz, vp]
+    L.mc_logdet_rule.restype = ci
     _lib = L
     return L
 
@@ -225,6 +230,25 @@ def slogdet_pivots(a: torch.Tensor, b: int = 0, update="native"):
                                 result.data_ptr(), work.data_ptr(), work.numel(),
                                 _stream_ptr(None, a.device))
     _check(st, "mc_logdet_pivots")
+    return read_result(result)[0], piv[:n]
+
+
+def slogdet_rule(a: torch.Tensor, rule="maxabs"):
+    """(Result, piv_col) of the plain FP64 condensation under a pivot-column
+    rule: "maxabs" (the paper's, Section 2.2), "first_nonzero" or
+    "closest_to_one" (the earlier rules of Section 1).  Synchronises."""
+    n = a.shape[0]
+    lda = _square_rows(a)
+    if a.dtype != torch.float64:
+        raise TypeError("the pivot-rule path takes FP64 matrices")
+    code = _RULES[rule] if isinstance(rule, str) else int(rule)
+    result = new_result(a.device)
+    work = new_workspace(n, a.device, torch.float64, "native", 0)
+    piv = torch.full((max(n, 1),), -1, dtype=torch.int32, device=a.device)
+    st = lib().mc_logdet_rule(a.data_ptr(), n, lda, code, piv.data_ptr(),
+                              result.data_ptr(), work.data_ptr(), work.numel(),
+                              _stream_ptr(None, a.device))
+    _check(st, "mc_logdet_rule")
     return read_result(result)[0], piv[:n]
 
 

@@ -859,10 +859,13 @@ extern "C" mc_status mc_logdet_backward_recompute(
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
 
+// `shared`: the call may use the device's scheduling state (lookahead's
+// side stream, the ordering of blocked calls); false keeps every kernel on
+// `stream` and creates no runtime object.
 static mc_status logdet_impl(const void* A, int64_t n, int64_t lda, int dtype,
                              int update, int64_t b, int32_t* piv_col,
                              mc_result* out, void* work, size_t work_bytes,
-                             void* stream)
+                             void* stream, bool shared = true)
 {
     if (n < 0 || n > kMaxN) return -2;
     if (n > 0 && A == nullptr) return -1;
@@ -894,14 +897,14 @@ static mc_status logdet_impl(const void* A, int64_t n, int64_t lda, int dtype,
             const BlkWork<double> w = blocked_carve<double>(work, n, b);
             e = launch_blocked<double>(static_cast<const double*>(A), n, lda,
                                        b, update, w, out, st, false,
-                                       g_lookahead_on.load());
+                                       shared && g_lookahead_on.load(), shared);
             // after the last panel, position s holds the column step s took
             if (e == hipSuccess && piv_col) e = launch_copy_i32(piv_col, w.perm, n, st);
         } else {
             const BlkWork<float> w = blocked_carve<float>(work, n, b);
             e = launch_blocked<float>(static_cast<const float*>(A), n, lda, b,
                                       update, w, out, st, false,
-                                      g_lookahead_on.load());
+                                      shared && g_lookahead_on.load(), shared);
             if (e == hipSuccess && piv_col) e = launch_copy_i32(piv_col, w.perm, n, st);
         }
     }
@@ -928,4 +931,26 @@ extern "C" mc_status mc_logdet_pivots(const void* A, int64_t n, int64_t lda,
                                     work, work_bytes, stream);
     // logdet_impl numbers `out` as argument 7; here it is argument 8
     return s == -7 ? -8 : (s == -8 ? -9 : s);
+}
+
+extern "C" mc_status mc_logdet_rule(const void* A, int64_t n, int64_t lda,
+                                    int rule, int32_t* piv_col, mc_result* out,
+                                    void* work, size_t work_bytes, void* stream)
+{
+    if (n < 0 || n > kMaxN) return -2;
+    if (n > 0 && A == nullptr) return -1;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (rule < MC_PIVOT_MAXABS || rule > MC_PIVOT_CLOSEST_TO_ONE) return -4;
+    if (out == nullptr) return -6;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0)
+        return launch_write_result(out, 0.0, 1.0, 0, st) == hipSuccess ? MC_OK
+                                                                       : MC_ERR_HIP;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -7;
+    if (work_bytes < plain_workspace_bytes(n)) return MC_ERR_WORKSPACE;
+    PlainWork w = plain_carve(work, n);
+    w.piv_col = piv_col;
+    const hipError_t e =
+        launch_plain_f64(static_cast<const double*>(A), n, lda, w, out, st, rule);
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }

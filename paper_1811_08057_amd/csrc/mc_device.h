@@ -24,7 +24,8 @@ enum : int {
 };
 
 struct PivotKey {
-    double absval; // |value|, -1 for "no candidate"
+    double absval; // the rule's score (|value| for the paper's rule), -inf
+                   // for "no candidate"; larger is better
     double value;  // the signed entry (the pivot keeps its sign)
     int colid;     // original column index (tie-break)
     int slot;      // where the entry sits in the current row
@@ -33,7 +34,7 @@ struct PivotKey {
 __device__ __forceinline__ PivotKey no_candidate()
 {
     PivotKey k;
-    k.absval = -1.0;
+    k.absval = -INFINITY;
     k.value = 0.0;
     k.colid = INT_MAX;
     k.slot = -1;
@@ -45,14 +46,27 @@ __device__ __forceinline__ bool better(const PivotKey& a, const PivotKey& b)
     return a.absval > b.absval || (a.absval == b.absval && a.colid < b.colid);
 }
 
+// Pivot-column rules.  The paper's rule is the largest |a| (Section 2.2);
+// Section 1 describes two earlier ones that it argues against: the first
+// non-zero entry of the row (Beliakov) and the non-zero entry whose |a| is
+// closest to 1 (Haque).  Each is a score, larger is better, with ties to
+// the smallest original column; the two earlier rules never take a zero.
+enum : int { kRuleMaxAbs = 0, kRuleFirstNonzero = 1, kRuleClosestToOne = 2 };
+
 // Offer one entry to a running key; returns false if the entry is not
 // finite (the caller records that).
+template <int RULE = kRuleMaxAbs>
 __device__ __forceinline__ bool offer(PivotKey& k, double v, int colid,
                                       int slot)
 {
     if (!isfinite(v)) return false;
     PivotKey c;
-    c.absval = fabs(v);
+    if (RULE == kRuleMaxAbs) {
+        c.absval = fabs(v);
+    } else {
+        if (v == 0.0) return true;
+        c.absval = RULE == kRuleFirstNonzero ? 0.0 : -fabs(fabs(v) - 1.0);
+    }
     c.value = v;
     c.colid = colid;
     c.slot = slot;

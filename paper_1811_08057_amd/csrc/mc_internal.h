@@ -83,8 +83,10 @@ int split_panel_set(int on);
 
 size_t plain_workspace_bytes(int64_t n);
 PlainWork plain_carve(void* work, int64_t n);
+// rule: kRuleMaxAbs (the paper's), kRuleFirstNonzero or kRuleClosestToOne.
 hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
-                            PlainWork w, mc_result* out, hipStream_t stream);
+                            PlainWork w, mc_result* out, hipStream_t stream,
+                            int rule = 0);
 
 // Copy n int32 values on the stream (a kernel, so that graph capture
 // records no memory-copy or memset node).

@@ -28,6 +28,7 @@ namespace mc {
 
 constexpr int kPlainThreads = 256;
 
+template <int RULE>
 __global__ void __launch_bounds__(kPlainThreads)
 plain_init(const double* __restrict__ A, int64_t n, PlainWork w)
 {
@@ -39,7 +40,7 @@ plain_init(const double* __restrict__ A, int64_t n, PlainWork w)
     bool bad = false;
     for (int64_t j = tid; j < n; j += kPlainThreads) {
         w.colid[j] = (int)j;
-        if (!offer(k, A[j], (int)j, (int)j)) bad = true;
+        if (!offer<RULE>(k, A[j], (int)j, (int)j)) bad = true;
     }
     k = block_argmax<kPlainThreads>(k, bad, sh, &shflag);
     if (tid == 0) {
@@ -64,6 +65,7 @@ plain_init(const double* __restrict__ A, int64_t n, PlainWork w)
 
 // src/lds: the matrix rows for this step (the caller's A at step 0, the
 // workspace afterwards).  dst is always the workspace.
+template <int RULE>
 __global__ void __launch_bounds__(kPlainThreads)
 plain_step(const double* src, int64_t lds, int64_t n, int64_t s,
            int rows_per_block, PlainWork w)
@@ -97,7 +99,7 @@ plain_step(const double* src, int64_t lds, int64_t n, int64_t s,
             const int64_t jj = (j == l) ? m - 1 : j;
             const double y = fma(-c, rc[jj], src[i * lds + jj]);
             W[i * ldw + j] = y;
-            if (!offer(k, y, w.colid[j], (int)j)) bad = true;
+            if (!offer<RULE>(k, y, w.colid[j], (int)j)) bad = true;
         }
         k = block_argmax<kPlainThreads>(k, bad, sh, &shflag);
         if (tid == 0) {
@@ -206,12 +208,16 @@ plain_finalize(int64_t n, PlainWork w, mc_result* out)
 
 // ---------------------------------------------------------------- launcher
 
-hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
-                            PlainWork w, mc_result* out, hipStream_t stream)
+// The per-step launches (plain_init first when `init`).
+template <int RULE>
+static void plain_steps(const double* A, int64_t n, int64_t lda, PlainWork w,
+                        hipStream_t stream, bool init)
 {
-    hipLaunchKernelGGL(plain_init, dim3(1), dim3(kPlainThreads), 0, stream, A,
-                       n, w);
-    const ProfMark pm = prof_begin(stream);
+    if (init) {
+        hipLaunchKernelGGL(plain_init<RULE>, dim3(1), dim3(kPlainThreads), 0,
+                           stream, A, n, w);
+        return;
+    }
     for (int64_t s = 0; s + 1 < n; ++s) {
         const int64_t m = n - s;
         const int64_t bulk_rows = m - 2; // rows s+2 .. n-1
@@ -223,10 +229,30 @@ hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
         const int64_t blocks = 1 + (bulk_rows + rpb - 1) / rpb;
         const double* src = (s == 0) ? A : w.W;
         const int64_t lds = (s == 0) ? lda : w.ldw;
-        hipLaunchKernelGGL(plain_step, dim3((unsigned)blocks),
+        hipLaunchKernelGGL(plain_step<RULE>, dim3((unsigned)blocks),
                            dim3(kPlainThreads), 0, stream, src, lds, n, s, rpb,
                            w);
     }
+}
+
+static void plain_dispatch(const double* A, int64_t n, int64_t lda, PlainWork w,
+                           hipStream_t stream, int rule, bool init)
+{
+    if (rule == kRuleFirstNonzero)
+        plain_steps<kRuleFirstNonzero>(A, n, lda, w, stream, init);
+    else if (rule == kRuleClosestToOne)
+        plain_steps<kRuleClosestToOne>(A, n, lda, w, stream, init);
+    else
+        plain_steps<kRuleMaxAbs>(A, n, lda, w, stream, init);
+}
+
+hipError_t launch_plain_f64(const double* A, int64_t n, int64_t lda,
+                            PlainWork w, mc_result* out, hipStream_t stream,
+                            int rule)
+{
+    plain_dispatch(A, n, lda, w, stream, rule, true);
+    const ProfMark pm = prof_begin(stream);
+    plain_dispatch(A, n, lda, w, stream, rule, false);
     // live entries updated over all steps: sum of (m-1)^2, m = n .. 2
     const double nn = (double)(n - 1);
     const double entries = nn * (nn + 1.0) * (2.0 * nn + 1.0) / 6.0;

@@ -81,3 +81,19 @@ def test_binding_rejects_host_tensors():
         mc.logdet_async(torch.eye(3, dtype=torch.float64),
                         torch.empty(3, dtype=torch.float64),
                         torch.empty(10, dtype=torch.uint8))
+
+
+def test_rule_call_argument_checks():
+    lib = mc.lib()
+    fake = ctypes.c_void_p(256)
+    out = ctypes.c_void_p(512)
+    piv = ctypes.c_void_p(1024)
+    assert lib.mc_logdet_rule(fake, -1, 1, 0, piv, out, fake, 1 << 20, None) == -2
+    assert lib.mc_logdet_rule(None, 4, 4, 0, piv, out, fake, 1 << 20, None) == -1
+    assert lib.mc_logdet_rule(fake, 4, 3, 0, piv, out, fake, 1 << 20, None) == -3
+    for bad_rule in (-1, 3):
+        assert lib.mc_logdet_rule(fake, 4, 4, bad_rule, piv, out, fake, 1 << 20,
+                                  None) == -4
+    assert lib.mc_logdet_rule(fake, 4, 4, 2, piv, None, fake, 1 << 20, None) == -6
+    assert lib.mc_logdet_rule(fake, 4, 4, 1, None, out, None, 1 << 20, None) == -7
+    assert lib.mc_logdet_rule(fake, 4, 4, 1, None, out, fake, 16, None) == -100
