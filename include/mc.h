@@ -83,6 +83,8 @@ typedef int mc_status;
 #define MC_ERR_WORKSPACE (-100)   /* work_bytes below the query's size   */
 #define MC_ERR_HIP (-101)         /* a HIP launch or query failed        */
 #define MC_ERR_UNSUPPORTED (-102) /* combination not provided            */
+#define MC_ERR_TOO_LARGE (-103)   /* mc_logdet_noalloc: the workspace the
+                                     call needs exceeds MC_NOALLOC_BYTES  */
 
 #define MC_INFO_NONFINITE (-1)
 #define MC_INFO_BADARG (-3) /* batched: this matrix's n / lda / pointer invalid */
@@ -156,6 +158,30 @@ mc_status mc_logdet_pivots(const void* A, int64_t n, int64_t lda, int dtype,
                            int update, int64_t b, int32_t* piv_col,
                            mc_result* out, void* work, size_t work_bytes,
                            void* stream);
+
+/*
+ * mc_logdet without a workspace argument, for callers that cannot allocate
+ * device memory: code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The library allocates nothing for it either: the
+ * workspace is a fixed device array of MC_NOALLOC_BYTES inside the library,
+ * one per GPU, held until the process ends.  Calls that need more than that
+ * (mc_logdet_workspace(n, dtype, update, b) > MC_NOALLOC_BYTES; n = 2048 fits
+ * every path) return MC_ERR_TOO_LARGE before anything is enqueued.
+ *
+ * Arguments, results and error numbering as mc_logdet (without work and
+ * work_bytes).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams, or different host threads without
+ * stream ordering) race and must not be made.  The blocked path runs with
+ * lookahead off and creates no stream or event (mc_lookahead_enable does not
+ * apply); it is not ordered against other blocked calls on the device, which
+ * must not overlap it either.  The first call on each device looks the
+ * array's device address up (hipGetSymbolAddress); make that first call
+ * outside graph capture.
+ */
+#define MC_NOALLOC_BYTES (40u * 1024u * 1024u)
+mc_status mc_logdet_noalloc(const void* A, int64_t n, int64_t lda, int dtype,
+                            int update, int64_t b, mc_result* out,
+                            void* stream);
 
 /*
  * Pivot-column rules inside the pivot row.  The paper's rule is the column

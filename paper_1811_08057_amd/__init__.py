@@ -42,7 +42,8 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_logdet_backward", "mc_lookahead_enable", "mc_default_panel",
            "mc_split_panel_enable", "mc_logdet_pivots",
            "mc_logdet_backward_recompute_workspace",
-           "mc_logdet_backward_recompute", "mc_logdet_rule")
+           "mc_logdet_backward_recompute", "mc_logdet_rule",
+           "mc_logdet_noalloc")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -126,6 +127,8 @@ def lib() -> ctypes.CDLL:
     L.mc_logdet_backward_recompute.restype = ci
     L.mc_logdet_rule.argtypes = [vp, i64, i64, ci, vp, vp, vp, sz, vp]
     L.mc_logdet_rule.restype = ci
+    L.mc_logdet_noalloc.argtypes = [vp, i64, i64, ci, ci, i64, vp, vp]
+    L.mc_logdet_noalloc.restype = ci
     _lib = L
     return L
 

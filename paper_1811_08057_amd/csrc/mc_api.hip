@@ -241,6 +241,8 @@ extern "C" const char* mc_status_string(mc_status status)
     case MC_ERR_WORKSPACE: return "workspace too small";
     case MC_ERR_HIP: return "HIP launch or query failed";
     case MC_ERR_UNSUPPORTED: return "unsupported combination of arguments";
+    case MC_ERR_TOO_LARGE:
+        return "matrix too large for the library's fixed scratch array (MC_NOALLOC_BYTES)";
     default: break;
     }
     if (status < 0 && status > -20) return "invalid argument";
@@ -910,6 +912,16 @@ static mc_status logdet_impl(const void* A, int64_t n, int64_t lda, int dtype,
     }
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
+
+namespace mc {
+mc_status logdet_fixed_work(const void* A, int64_t n, int64_t lda, int dtype,
+                            int update, int64_t b, mc_result* out, void* work,
+                            size_t work_bytes, void* stream)
+{
+    return logdet_impl(A, n, lda, dtype, update, b, nullptr, out, work,
+                       work_bytes, stream, false);
+}
+} // namespace mc
 
 extern "C" mc_status mc_logdet(const void* A, int64_t n, int64_t lda,
                                int dtype, int update, int64_t b,

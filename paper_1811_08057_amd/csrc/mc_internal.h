@@ -129,4 +129,11 @@ hipError_t note_hip_error(hipError_t e);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// mc_logdet on a caller-provided workspace with no per-device scheduling
+// state: lookahead off, not ordered against other blocked calls, no stream
+// or event created.  Same argument checks and numbering as mc_logdet.
+mc_status logdet_fixed_work(const void* A, int64_t n, int64_t lda, int dtype,
+                            int update, int64_t b, mc_result* out, void* work,
+                            size_t work_bytes, void* stream);
+
 } // namespace mc
