@@ -82,6 +82,16 @@ def parse():
                         "three times (the reference kernel for scaling the "
                         "HBM counters FETCH_SIZE / WRITE_SIZE)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--grad", action="store_true",
+                   help="batch workloads: time forward + backward (one "
+                        "batched factor launch, the blocked factor call for "
+                        "the largest members, one batched backward launch) "
+                        "instead of the forward graph")
+    p.add_argument("--study", default=None, choices=["pivot-rules"],
+                   help="pivot-rules: accuracy of the three pivot-column "
+                        "rules (Section 1, Section 2.2) on the GPU's plain "
+                        "path against exact determinants; prints one JSON "
+                        "line and exits")
     return p.parse_args()
 
 
@@ -322,6 +332,76 @@ def mfma_peak(prec: str):
             "bf16x3": (BF16_PEAK_TFS, 3)}[prec]
 
 
+def run_batch_grad(args, mc, torch, sizes, mats, devs, allexp, update, stream):
+    """Forward + backward of sum_k log|det A_k| through the batched autograd
+    function: the batched factor launch for the members below
+    BatchedPlan.BLOCKED_MIN_N rows, the blocked factor call for each larger
+    one, and one batched backward launch for all members."""
+    import numpy as np
+
+    prec = args.precision
+    leaves = [d.clone().requires_grad_(True) for d in devs]
+
+    def step():
+        for x in leaves:
+            x.grad = None
+        signs, logabs = mc.slogdet_batched_autograd(leaves, update=update)
+        logabs.sum().backward()
+        return signs, logabs
+
+    steps = args.steps if args.steps is not None else 10
+    warmup = args.warmup if args.warmup is not None else 2
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        signs, logabs = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fwd_flops = sum(2.0 * n ** 3 / 3.0 for n in sizes)
+    bwd_flops = sum(4.0 * n ** 3 / 3.0 for n in sizes)
+    worst = gworst = None
+    signs_ok = None
+    if allexp is not None:
+        exp = allexp["f64" if prec == "f64" else "f32"]
+        la = logabs.detach().cpu().numpy()
+        sg = signs.cpu().numpy()
+        worst = max(abs(float(g) - e["logabsdet"]) / max(abs(e["logabsdet"]), 1.0)
+                    for g, e in zip(la, exp))
+        signs_ok = all(float(g) == e["sign"] for g, e in zip(sg, exp))
+        if "grad_samples" in allexp:
+            key = "f64" if prec == "f64" else "f32"
+            gworst = 0.0
+            for x, smp in zip(leaves, allexp["grad_samples"]):
+                g = x.grad.double().cpu().numpy()
+                ref = np.array(smp[key])
+                got = np.array([g[i, j] for i, j in smp["ij"]])
+                gworst = max(gworst, float(np.abs(got - ref).max() / np.abs(ref).max()))
+    peak, mult = mfma_peak(prec)
+    ach = mult * (fwd_flops + bwd_flops) / (ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": len(sizes) / (ms * 1e-3), "unit": "log-dets/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "batch": len(sizes),
+                   "n_min": min(sizes), "n_max": max(sizes), "precision": prec,
+                   "path": "batched forward + backward (autograd)"},
+        "gflops": (fwd_flops + bwd_flops) / (ms * 1e-3) / 1e9,
+        "rel_err_vs_oracle": worst, "sign_matches_oracle": signs_ok,
+        "grad_sampled_rel_err_vs_oracle": gworst,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak,
+                     "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                     "note": "forward 2n^3/3 + backward 4n^3/3 flops per member "
+                             "over the whole step"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args, mc, torch, synth, spec, dev, stream):
     """The batch as one captured graph, replayed: one persistent batched
     launch for the members below BatchedPlan.BLOCKED_MIN_N rows and the
@@ -337,6 +417,9 @@ def run_batch(args, mc, torch, synth, spec, dev, stream):
     if prec != "f64":
         check_input(allexp, "sha256_f32", [m.astype("float32") for m in mats])
     devs = [torch.from_numpy(m).to(dev, dtype) for m in mats]
+    if args.grad:
+        run_batch_grad(args, mc, torch, sizes, mats, devs, allexp, update, stream)
+        return
     plan = mc.BatchedPlan(devs, b=-1, update=update)
     plan.capture()
     steps = args.steps if args.steps is not None else 20
@@ -409,6 +492,91 @@ def run_batch(args, mc, torch, synth, spec, dev, stream):
     print(json.dumps(out), flush=True)
 
 
+def _bareiss_logabs(a) -> tuple:
+    """(sign, log|det|) of a float matrix exactly: its doubles scaled to
+    integers by one power of two, then fraction-free (Bareiss) elimination
+    with exact integer divisions."""
+    import math
+    from fractions import Fraction
+
+    n = a.shape[0]
+    fr = [[Fraction(float(x)) for x in row] for row in a]
+    scale = 1
+    for row in fr:
+        for x in row:
+            scale = max(scale, x.denominator)
+    m = [[int(x * scale) for x in row] for row in fr]
+    sign, prev = 1, 1
+    for k in range(n - 1):
+        if m[k][k] == 0:
+            for i in range(k + 1, n):
+                if m[i][k] != 0:
+                    m[k], m[i] = m[i], m[k]
+                    sign = -sign
+                    break
+            else:
+                return 0, -math.inf
+        for i in range(k + 1, n):
+            for j in range(k + 1, n):
+                m[i][j] = (m[i][j] * m[k][k] - m[i][k] * m[k][j]) // prev
+        prev = m[k][k]
+    d = m[n - 1][n - 1] * sign
+    if d == 0:
+        return 0, -math.inf
+    # log|d| of a big integer, then undo the scaling (scale^n)
+    bits = abs(d).bit_length()
+    shift = max(0, bits - 60)
+    la = math.log(abs(d) >> shift) + shift * math.log(2.0)
+    return (1 if d > 0 else -1), la - n * math.log(scale)
+
+
+def run_pivot_study(args, mc, torch, dev):
+    """The three pivot-column rules on the GPU's plain FP64 path (Section 1:
+    first non-zero, closest to 1; Section 2.2: largest |a|), relative error
+    of log|det| against the exact determinant, over seeded matrix
+    families."""
+    import numpy as np
+
+    families = {
+        "sec22": ("rows drawn from {+-1e-10, +-2.01} plus 1e-3 N(0,1) noise "
+                  "(the Section 2.2 example)",
+                  lambda g, n: g.choice([1e-10, 2.01, -2.01, -1e-10], (n, n))
+                  + 1e-3 * g.standard_normal((n, n))),
+        "uniform": ("i.i.d. U[-1, 1]",
+                    lambda g, n: g.uniform(-1.0, 1.0, (n, n))),
+        "graded": ("U[-1, 1] with each row scaled by 10^U[-6, 6]",
+                   lambda g, n: 10.0 ** g.uniform(-6.0, 6.0, (n, 1))
+                   * g.uniform(-1.0, 1.0, (n, n))),
+    }
+    rules = ["maxabs", "first_nonzero", "closest_to_one"]
+    sizes = [8, 32, 64]
+    trials = args.steps if args.steps is not None else 10
+    rows = []
+    for fam, (desc, make) in families.items():
+        for n in sizes:
+            errs = {r: [] for r in rules}
+            for t in range(trials):
+                g = np.random.default_rng(1000 * n + t)
+                a = make(g, n)
+                sgn, ref = _bareiss_logabs(a)
+                ad = torch.from_numpy(a).to(dev)
+                for r in rules:
+                    got, _ = mc.slogdet_rule(ad, r)
+                    bad = got.sign != sgn or not np.isfinite(got.logabsdet)
+                    errs[r].append(float("inf") if bad else
+                                   abs(got.logabsdet - ref) / max(abs(ref), 1.0))
+            for r in rules:
+                e = np.array(errs[r])
+                rows.append({"family": fam, "n": n, "rule": r, "trials": trials,
+                             "median_rel_err": float(np.median(e)),
+                             "max_rel_err": float(e.max())})
+            print(f"# {fam} n={n} done", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "pivot-rules", "path": "plain FP64 (mc_logdet_rule)",
+                      "reference": "exact determinant (Bareiss on the doubles' exact values)",
+                      "families": {k: v[0] for k, v in families.items()},
+                      "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -434,6 +602,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb,
                           "launches": 3}), flush=True)
+        return
+    if args.study == "pivot-rules":
+        run_pivot_study(args, mc, torch, dev)
         return
     spec = synth.CONFIGS[args.workload]
     stream = torch.cuda.current_stream(dev)

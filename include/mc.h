@@ -324,6 +324,71 @@ mc_status mc_logdet_batched(const void* const* A_array, const int64_t* n_array,
                             void* stream);
 
 /*
+ * Batched factor call: mc_logdet_batched with each matrix condensed in
+ * place and its factors kept, exactly as mc_logdet_factor leaves them
+ * (A_k,in[:, perm_k] = L_k U_k, L\U in A_k; Section 2.3 and Figure 6 step
+ * 4.8), so that mc_logdet_batched_backward (or mc_logdet_backward per
+ * matrix) can use them.  One persistent launch (plus a one-block setup
+ * launch), graph-capturable.
+ *
+ * A_array     device array of `batch` device pointers; overwritten.
+ * perm_array  device array of `batch` device pointers to n_k int32 each
+ *             (output; n_k = 0: may be NULL).
+ * Other arguments as mc_logdet_batched (error numbering: A_array 1,
+ * n_array 2, lda_array 3, perm_array 4, batch 5, n_max 6, dtype 7,
+ * update 8, b 9, out 10, work 11).  The workspace holds no copy of the
+ * matrices (it is smaller than mc_logdet_batched's).  After a singular or
+ * non-finite result, that matrix and its perm are unspecified.
+ */
+size_t mc_logdet_batched_factor_workspace(int64_t batch, int64_t n_max,
+                                          int dtype, int update, int64_t b);
+mc_status mc_logdet_batched_factor(void* const* A_array, const int64_t* n_array,
+                                   const int64_t* lda_array,
+                                   int32_t* const* perm_array, int64_t batch,
+                                   int64_t n_max, int dtype, int update,
+                                   int64_t b, mc_result* out, void* work,
+                                   size_t work_bytes, void* stream);
+
+/*
+ * Batched backward call: G_k = g_k * A_k^{-T} for every member, from the
+ * factors of mc_logdet_factor or mc_logdet_batched_factor, in one
+ * persistent launch (plus a one-block setup launch; graph-capturable).  The
+ * work is split into (matrix, 64-column block) items taken largest matrix
+ * first; each item runs the two triangular substitutions of its columns of
+ * A^{-1} = Q U^{-1} L^{-1} with the block updates on the matrix cores.
+ *
+ * LU_array, perm_array  device arrays of `batch` device pointers: factors
+ *             (row stride ld_array[k]) and perms; read only.
+ * n_array, ld_array     device arrays of `batch` int64.
+ * n_max       host value, 0 <= n_max <= 16384: an upper bound of every n_k
+ *             (members with n_k outside [0, n_max] are skipped, G_k left
+ *             untouched).
+ * dtype       mc_dtype of the factors and gradients.
+ * grad_out    device array of `batch` doubles (g_k), or NULL for g_k = 1.
+ * fwd         device array of the `batch` factor results, or NULL; a member
+ *             whose info != 0 gets an all-NaN G_k.
+ * G_array     device array of `batch` device pointers (output, n_k x n_k,
+ *             row stride ldg_array[k]); must not overlap the factors.
+ *             G_k's rows also serve as the item's working storage.
+ * work        >= mc_logdet_batched_backward_workspace(batch, n_max, dtype)
+ *             bytes, 256-byte aligned (the item queue).
+ * Error numbering: LU_array 1, n_array 2, ld_array 3, perm_array 4,
+ * batch 5, n_max 6, dtype 7, G_array 10, ldg_array 11, work 12.
+ */
+size_t mc_logdet_batched_backward_workspace(int64_t batch, int64_t n_max,
+                                            int dtype);
+mc_status mc_logdet_batched_backward(const void* const* LU_array,
+                                     const int64_t* n_array,
+                                     const int64_t* ld_array,
+                                     const int32_t* const* perm_array,
+                                     int64_t batch, int64_t n_max, int dtype,
+                                     const double* grad_out,
+                                     const mc_result* fwd,
+                                     void* const* G_array,
+                                     const int64_t* ldg_array, void* work,
+                                     size_t work_bytes, void* stream);
+
+/*
  * The batched path's tuning table: for size buckets n <= 64, 128, 256, 512,
  * 1024 and larger, a panel width b_k (1..128) and a trailing-update tile
  * edge tile_k (32 or 64).  One table per (dtype, update), process-wide,

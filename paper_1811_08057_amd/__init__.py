@@ -43,7 +43,9 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_split_panel_enable", "mc_logdet_pivots",
            "mc_logdet_backward_recompute_workspace",
            "mc_logdet_backward_recompute", "mc_logdet_rule",
-           "mc_logdet_noalloc")
+           "mc_logdet_noalloc", "mc_logdet_batched_factor_workspace",
+           "mc_logdet_batched_factor", "mc_logdet_batched_backward_workspace",
+           "mc_logdet_batched_backward")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -129,6 +131,16 @@ def lib() -> ctypes.CDLL:
     L.mc_logdet_rule.restype = ci
     L.mc_logdet_noalloc.argtypes = [vp, i64, i64, ci, ci, i64, vp, vp]
     L.mc_logdet_noalloc.restype = ci
+    L.mc_logdet_batched_factor_workspace.argtypes = [i64, i64, ci, ci, i64]
+    L.mc_logdet_batched_factor_workspace.restype = sz
+    L.mc_logdet_batched_factor.argtypes = [vp, vp, vp, vp, i64, i64, ci, ci, i64,
+                                           vp, vp, sz, vp]
+    L.mc_logdet_batched_factor.restype = ci
+    L.mc_logdet_batched_backward_workspace.argtypes = [i64, i64, ci]
+    L.mc_logdet_batched_backward_workspace.restype = sz
+    L.mc_logdet_batched_backward.argtypes = [vp, vp, vp, vp, i64, i64, ci, vp, vp,
+                                             vp, vp, vp, sz, vp]
+    L.mc_logdet_batched_backward.restype = ci
     _lib = L
     return L
 
@@ -408,6 +420,80 @@ class BatchedPlan:
         return out
 
 
+def _ptr_array(tensors, device) -> torch.Tensor:
+    return torch.tensor([t.data_ptr() for t in tensors], dtype=torch.int64,
+                        device=device)
+
+
+def factor_batched(mats, b: int = -1, update="native"):
+    """Factor copies of the matrices in one persistent launch
+    (mc_logdet_batched_factor): returns (lus, perms, result) with
+    mats[k][:, perms[k]] = L U (L\\U in lus[k]) and result the device buffer
+    of the batch's mc_result structs (not yet synchronised)."""
+    if not mats:
+        raise ValueError("empty batch")
+    dev, dt = mats[0].device, mats[0].dtype
+    lus = [m.detach().contiguous().clone() for m in mats]
+    for m in lus:
+        _square_rows(m)
+        if m.dtype != dt or m.device != dev:
+            raise ValueError("all matrices need one dtype and device")
+    ns = [m.shape[0] for m in lus]
+    perms = [torch.empty(max(n, 1), dtype=torch.int32, device=dev) for n in ns]
+    n_max = max(ns)
+    nb = lib().mc_logdet_batched_factor_workspace(len(lus), n_max, _dtype_of(dt),
+                                                 _update_code(update), b)
+    if nb == 0:
+        raise MCError("unsupported combination for the batched factor call")
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    res = new_result(dev, len(lus))
+    ptrs = _ptr_array(lus, dev)
+    nsd = torch.tensor(ns, dtype=torch.int64, device=dev)
+    ldas = torch.tensor([max(n, 1) for n in ns], dtype=torch.int64, device=dev)
+    pp = _ptr_array(perms, dev)
+    st = lib().mc_logdet_batched_factor(
+        ptrs.data_ptr(), nsd.data_ptr(), ldas.data_ptr(), pp.data_ptr(), len(lus),
+        n_max, _dtype_of(dt), _update_code(update), b, res.data_ptr(),
+        work.data_ptr(), work.numel(), _stream_ptr(None, dev))
+    _check(st, "mc_logdet_batched_factor")
+    return lus, [p[:n] for p, n in zip(perms, ns)], res
+
+
+def backward_batched(lus, perms, grad_out: Optional[torch.Tensor] = None,
+                     fwd: Optional[torch.Tensor] = None) -> list:
+    """g_k * A_k^{-T} for every member from stored factors, in one persistent
+    launch (mc_logdet_batched_backward).  grad_out: device float64 tensor of
+    one entry per member (None: 1); fwd: the factor calls' device results
+    (members whose info != 0 get an all-NaN gradient)."""
+    if not lus:
+        return []
+    dev, dt = lus[0].device, lus[0].dtype
+    ns = [m.shape[0] for m in lus]
+    n_max = max(ns)
+    grads = [torch.empty_like(m) for m in lus]
+    nb = lib().mc_logdet_batched_backward_workspace(len(lus), n_max, _dtype_of(dt))
+    if nb == 0:
+        raise MCError("unsupported combination for the batched backward call")
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    lp = _ptr_array(lus, dev)
+    gp = _ptr_array(grads, dev)
+    pp = _ptr_array(perms, dev)
+    nsd = torch.tensor(ns, dtype=torch.int64, device=dev)
+    lds = torch.tensor([_square_rows(m) for m in lus], dtype=torch.int64, device=dev)
+    ldg = torch.tensor([_square_rows(g) for g in grads], dtype=torch.int64, device=dev)
+    g_ptr = None
+    if grad_out is not None:
+        grad_out = grad_out.detach().to(dev, torch.float64).contiguous()
+        g_ptr = grad_out.data_ptr()
+    st = lib().mc_logdet_batched_backward(
+        lp.data_ptr(), nsd.data_ptr(), lds.data_ptr(), pp.data_ptr(), len(lus),
+        n_max, _dtype_of(dt), g_ptr, fwd.data_ptr() if fwd is not None else None,
+        gp.data_ptr(), ldg.data_ptr(), work.data_ptr(), work.numel(),
+        _stream_ptr(None, dev))
+    _check(st, "mc_logdet_batched_backward")
+    return grads
+
+
 def logdet_batched(mats, b: int = -1, update="native") -> list:
     """(sign, log|det|, info) of every matrix of a batch (synchronises)."""
     plan = BatchedPlan(mats, b=b, update=update)
@@ -557,3 +643,53 @@ def slogdet_autograd(a: torch.Tensor, b: int = -1, update="native",
                      mem_budget: Optional[int] = None):
     """Differentiable (sign, log|det A|) as device tensors (no host sync)."""
     return MCLogDet.apply(a, b, update, mem_budget)
+
+
+# ------------------------------------------------------ batched autograd
+
+class MCLogDetBatched(torch.autograd.Function):
+    """(signs, log|det A_k|) of a batch, with d log|det A_k| / dA_k =
+    A_k^{-T}.  Forward keeps every member's factors: members of at least
+    ``BatchedPlan.BLOCKED_MIN_N`` rows through the single-matrix factor call
+    (the whole-GPU blocked path), the rest through one batched factor
+    launch.  Backward is one batched backward launch over all members
+    (failed members get NaN gradients, decided on the device)."""
+
+    @staticmethod
+    def forward(ctx, b, update, *mats):
+        mats = [m.detach() for m in mats]
+        dev = mats[0].device
+        big = [k for k, m in enumerate(mats) if m.shape[0] >= BatchedPlan.BLOCKED_MIN_N]
+        small = [k for k in range(len(mats)) if k not in set(big)]
+        lus = [None] * len(mats)
+        perms = [None] * len(mats)
+        res = [None] * len(mats)
+        for k in big:
+            lus[k], perms[k], res[k] = factor(mats[k], b=b, update=update)
+        if small:
+            sl, sp, sr = factor_batched([mats[k] for k in small], b=b, update=update)
+            for i, k in enumerate(small):
+                lus[k], perms[k], res[k] = sl[i], sp[i], sr[i:i + 1]
+        fwd = torch.cat(res).to(dev)
+        ctx.save_for_backward(fwd, *lus, *perms)
+        ctx.count = len(mats)
+        signs = fwd[:, 1].clone()
+        logabs = fwd[:, 0].clone()
+        ctx.mark_non_differentiable(signs)
+        return signs, logabs
+
+    @staticmethod
+    def backward(ctx, gsigns, glogabs):
+        saved = ctx.saved_tensors
+        fwd, c = saved[0], ctx.count
+        lus, perms = list(saved[1:1 + c]), list(saved[1 + c:1 + 2 * c])
+        if glogabs is None:
+            glogabs = torch.zeros(c, dtype=torch.float64, device=fwd.device)
+        grads = backward_batched(lus, perms, grad_out=glogabs, fwd=fwd)
+        return (None, None, *grads)
+
+
+def slogdet_batched_autograd(mats, b: int = -1, update="native"):
+    """Differentiable (signs, log|det|) of a list of device matrices, as two
+    device tensors of len(mats) entries (no host synchronisation)."""
+    return MCLogDetBatched.apply(b, update, *mats)

@@ -10,6 +10,7 @@
 
 #include "mc.h"
 #include "mc_batched.h"
+#include "mc_batched_bwd.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -402,10 +403,12 @@ static mc_status batched_call(const void* const* A_array, const int64_t* n_array
                               const int64_t* lda_array, int64_t batch,
                               int64_t n_max, int dtype, int update,
                               const TuneTable& t, mc_result* out, void* work,
-                              size_t work_bytes, hipStream_t st)
+                              size_t work_bytes, hipStream_t st,
+                              int32_t* const* perm_array = nullptr)
 {
+    const bool with_w = perm_array == nullptr;
     const size_t need = batched_header_bytes(batch) +
-                        (size_t)batch * batched_region_bytes(n_max, dtype, t);
+                        (size_t)batch * batched_region_bytes(n_max, dtype, t, with_w);
     if (work_bytes < need) return MC_ERR_WORKSPACE;
     BatchArgs a;
     a.A_array = A_array;
@@ -419,8 +422,9 @@ static mc_status batched_call(const void* const* A_array, const int64_t* n_array
     a.counter = reinterpret_cast<int*>(base);
     a.order = reinterpret_cast<int*>(base + align_up(sizeof(int) * 64, 256));
     a.regions = base + batched_header_bytes(batch);
-    a.region_stride = batched_region_bytes(n_max, dtype, t);
+    a.region_stride = batched_region_bytes(n_max, dtype, t, with_w);
     a.out = out;
+    a.perm_array = perm_array;
     const hipError_t e = launch_batched(a, dtype, batched_lds_bytes(dtype, t), st);
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
@@ -447,6 +451,90 @@ extern "C" mc_status mc_logdet_batched(const void* const* A_array,
     return batched_call(A_array, n_array, lda_array, batch, n_max, dtype,
                         update, effective_table(dtype, update, b), out, work,
                         work_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t mc_logdet_batched_factor_workspace(int64_t batch, int64_t n_max,
+                                                     int dtype, int update, int64_t b)
+{
+    if (batch < 0 || n_max < 0 || n_max > kMaxN || b == 0 || b > kMaxPanel)
+        return 0;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return 0;
+    if (update < 0 || update > 2 || !batched_supported(dtype, update)) return 0;
+    const TuneTable t = effective_table(dtype, update, b);
+    return batched_header_bytes(batch) +
+           (size_t)batch * batched_region_bytes(n_max, dtype, t, false);
+}
+
+extern "C" mc_status mc_logdet_batched_factor(void* const* A_array, const int64_t* n_array,
+                                              const int64_t* lda_array,
+                                              int32_t* const* perm_array, int64_t batch,
+                                              int64_t n_max, int dtype, int update,
+                                              int64_t b, mc_result* out, void* work,
+                                              size_t work_bytes, void* stream)
+{
+    if (batch < 0) return -5;
+    if (batch > 0 && A_array == nullptr) return -1;
+    if (batch > 0 && n_array == nullptr) return -2;
+    if (batch > 0 && lda_array == nullptr) return -3;
+    if (batch > 0 && perm_array == nullptr) return -4;
+    if (n_max < 0 || n_max > kMaxN) return -6;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -7;
+    if (update < MC_UPDATE_NATIVE || update > MC_UPDATE_BF16X3) return -8;
+    if (b == 0 || b > kMaxPanel) return -9;
+    if (!batched_supported(dtype, update)) return MC_ERR_UNSUPPORTED;
+    if (batch > 0 && out == nullptr) return -10;
+    if (batch == 0) return MC_OK;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -11;
+    return batched_call(reinterpret_cast<const void* const*>(A_array), n_array, lda_array,
+                        batch, n_max, dtype, update, effective_table(dtype, update, b),
+                        out, work, work_bytes, static_cast<hipStream_t>(stream),
+                        perm_array);
+}
+
+// Largest n_max of the batched backward (its row permutation stages one
+// row in LDS).
+static constexpr int64_t kBatchedBwdMaxN = 16384;
+
+extern "C" size_t mc_logdet_batched_backward_workspace(int64_t batch, int64_t n_max,
+                                                      int dtype)
+{
+    if (batch < 0 || n_max < 0 || n_max > kBatchedBwdMaxN) return 0;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return 0;
+    return batched_bwd_workspace_bytes(batch, n_max);
+}
+
+extern "C" mc_status mc_logdet_batched_backward(
+    const void* const* LU_array, const int64_t* n_array, const int64_t* ld_array,
+    const int32_t* const* perm_array, int64_t batch, int64_t n_max, int dtype,
+    const double* grad_out, const mc_result* fwd, void* const* G_array,
+    const int64_t* ldg_array, void* work, size_t work_bytes, void* stream)
+{
+    if (batch < 0) return -5;
+    if (batch > 0 && LU_array == nullptr) return -1;
+    if (batch > 0 && n_array == nullptr) return -2;
+    if (batch > 0 && ld_array == nullptr) return -3;
+    if (batch > 0 && perm_array == nullptr) return -4;
+    if (n_max < 0 || n_max > kBatchedBwdMaxN) return -6;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -7;
+    if (batch > 0 && G_array == nullptr) return -10;
+    if (batch > 0 && ldg_array == nullptr) return -11;
+    if (batch == 0) return MC_OK;
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -12;
+    if (work_bytes < batched_bwd_workspace_bytes(batch, n_max)) return MC_ERR_WORKSPACE;
+    BatchedBwdArgs a{};
+    a.LU_array = LU_array;
+    a.n_array = n_array;
+    a.ld_array = ld_array;
+    a.perm_array = perm_array;
+    a.batch = batch;
+    a.n_max = n_max;
+    a.grad_out = grad_out;
+    a.fwd = fwd;
+    a.G_array = G_array;
+    a.ldg_array = ldg_array;
+    const hipError_t e = launch_batched_backward(a, dtype, work,
+                                                 static_cast<hipStream_t>(stream));
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
 
 extern "C" mc_status mc_tune_get(int dtype, int update, int64_t* b, int* tile)

@@ -36,9 +36,13 @@ struct BatchArgs {
     int* counter; // queue head
     int* order;   // matrices by decreasing size
     mc_result* out;
+    // the factor call: device array of each matrix's perm output (the
+    // matrices in A_array are then factored in place); null otherwise
+    int32_t* const* perm_array = nullptr;
 };
 
-size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t);
+size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t,
+                            bool with_w = true);
 size_t batched_lds_bytes(int dtype, const TuneTable& t);
 hipError_t launch_batched(const BatchArgs& a, int dtype, size_t lds_bytes,
                           hipStream_t stream);

@@ -37,12 +37,14 @@ __host__ __device__ inline int64_t bat_ldw(int64_t n, int elem)
 
 __host__ __device__ inline size_t bat_align(size_t x) { return (x + 255) / 256 * 256; }
 
-// Bytes of one matrix's region for size n and panel width b.
-__host__ __device__ inline size_t bat_region_bytes(int64_t n, int64_t b, int elem)
+// Bytes of one matrix's region for size n and panel width b (the factor
+// call works on the caller's matrix in place and keeps no copy W).
+__host__ __device__ inline size_t bat_region_bytes(int64_t n, int64_t b, int elem,
+                                                   bool with_w = true)
 {
     const size_t nblk = (size_t)((b + 15) / 16);
     size_t t = 0;
-    t += bat_align((size_t)elem * (size_t)n * (size_t)bat_ldw(n, elem)); // W
+    if (with_w) t += bat_align((size_t)elem * (size_t)n * (size_t)bat_ldw(n, elem)); // W
     t += bat_align((size_t)elem * (size_t)n * (size_t)b);               // L
     t += 3 * bat_align(sizeof(int) * (size_t)n);   // piv_pos, perm, colsrc
     t += bat_align(sizeof(double) * (size_t)n);    // piv_val
@@ -66,7 +68,7 @@ struct Region {
 
 template <typename T>
 __device__ inline Region<T> carve_region(unsigned char* base, int64_t n,
-                                         int64_t b)
+                                         int64_t b, bool with_w = true)
 {
     Region<T> r;
     const int elem = (int)sizeof(T);
@@ -77,7 +79,7 @@ __device__ inline Region<T> carve_region(unsigned char* base, int64_t n,
         p += bat_align(bytes);
         return q;
     };
-    r.W = reinterpret_cast<T*>(take((size_t)elem * n * r.ldw));
+    r.W = with_w ? reinterpret_cast<T*>(take((size_t)elem * n * r.ldw)) : nullptr;
     r.L = reinterpret_cast<T*>(take((size_t)elem * n * b));
     r.piv_pos = reinterpret_cast<int*>(take(sizeof(int) * n));
     r.perm = reinterpret_cast<int*>(take(sizeof(int) * n));
@@ -173,16 +175,19 @@ __device__ int wg_pivot_row(Region<T>& r, int64_t n, int64_t s, WgShared& sh)
 }
 
 // Step s inside the panel [s0, pend): exchange positions s, l in the
-// earlier panel rows; update the later panel rows (one wavefront per row).
+// earlier rows (the panel's own, or every row above when the factors are
+// kept: rows above hold U entries there); update the later panel rows (one
+// wavefront per row).
 template <typename T>
 __device__ void wg_panel_update(Region<T>& r, int64_t n, int64_t s,
-                                int64_t s0, int64_t pend, int64_t l)
+                                int64_t s0, int64_t pend, int64_t l,
+                                bool factor)
 {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     T* W = r.W;
     const int64_t ldw = r.ldw;
     if (l != s)
-        for (int64_t u = s0 + tid; u < s; u += kBT) {
+        for (int64_t u = (factor ? 0 : s0) + tid; u < s; u += kBT) {
             T* ru = W + u * ldw;
             const T a = ru[s];
             ru[s] = ru[l];
@@ -512,13 +517,18 @@ __device__ void wg_trailing<float>(Region<float>& r, int64_t n, int64_t s0,
     }
 }
 
-// Whole condensation of one matrix by one workgroup.
+// Whole condensation of one matrix by one workgroup.  With `perm_out`
+// (the factor call) the matrix A is condensed in place and keeps L\U as
+// mc_logdet_factor leaves it: A_in[:, perm] = L U, the multipliers of each
+// panel's rows below it stored at the panel's positions after its trailing
+// update, every exchange applied to the rows above.
 template <typename T>
 __device__ void wg_factor(const T* __restrict__ A, int64_t n, int64_t lda,
                           int64_t b, int tile, int update,
                           unsigned char* region, mc_result* out, WgShared& sh,
-                          T* lds)
+                          T* lds, int32_t* perm_out)
 {
+    const bool factor = perm_out != nullptr;
     const int tid = threadIdx.x;
     if (n == 0) {
         if (tid == 0) {
@@ -528,10 +538,16 @@ __device__ void wg_factor(const T* __restrict__ A, int64_t n, int64_t lda,
         }
         return;
     }
-    Region<T> r = carve_region<T>(region, n, b);
-    for (int64_t i = tid >> 6; i < n; i += kBT / kWave)
-        for (int64_t j = tid & 63; j < n; j += kWave)
-            r.W[i * r.ldw + j] = A[i * lda + j];
+    Region<T> r = carve_region<T>(region, n, b, !factor);
+    if (factor) {
+        r.W = const_cast<T*>(A);
+        r.ldw = lda;
+        r.perm = perm_out;
+    } else {
+        for (int64_t i = tid >> 6; i < n; i += kBT / kWave)
+            for (int64_t j = tid & 63; j < n; j += kWave)
+                r.W[i * r.ldw + j] = A[i * lda + j];
+    }
     for (int64_t j = tid; j < n; j += kBT) r.perm[j] = (int)j;
     __syncthreads();
 
@@ -547,7 +563,7 @@ __device__ void wg_factor(const T* __restrict__ A, int64_t n, int64_t lda,
         }
         for (int64_t s = s0; s < pend; ++s) {
             const int64_t l = r.piv_pos[s];
-            wg_panel_update<T>(r, n, s, s0, pend, l);
+            wg_panel_update<T>(r, n, s, s0, pend, l, factor);
             if (s + 1 < pend) {
                 st = wg_pivot_row<T>(r, n, s + 1, sh);
                 if (st != kStatusOk) {
@@ -560,6 +576,14 @@ __device__ void wg_factor(const T* __restrict__ A, int64_t n, int64_t lda,
         wg_perm<T>(r, n, s0, nb);
         wg_trsm<T>(r, n, s0, nb, lds);
         wg_trailing<T>(r, n, s0, nb, tile, update, lds);
+        if (factor) { // L21 to the panel's positions (the update read them)
+            for (int64_t e = tid; e < (n - pend) * nb; e += kBT) {
+                const int64_t row = pend + e / nb;
+                const int t = (int)(e % nb);
+                r.W[row * r.ldw + s0 + t] = r.L[(row - pend) * nb + t];
+            }
+            __syncthreads();
+        }
     }
 
     // compensated sum of log|p| and sign parity (as blk_finalize)
@@ -636,19 +660,29 @@ batched_persistent(BatchArgs a)
         const int64_t b = a.table.b[bk];
         const int tile = a.table.tile[bk];
         unsigned char* region = a.regions + (size_t)k * a.region_stride;
+        int32_t* perm = a.perm_array ? a.perm_array[k] : nullptr;
+        if (a.perm_array && n > 0 && perm == nullptr) {
+            if (threadIdx.x == 0) {
+                a.out[k].logabsdet = NAN;
+                a.out[k].sign = 0.0;
+                a.out[k].info = MC_INFO_BADARG;
+            }
+            continue;
+        }
         wg_factor<T>(static_cast<const T*>(a.A_array[k]), n, a.lda_array[k],
-                     b, tile, a.update, region, a.out + k, sh, lds);
+                     b, tile, a.update, region, a.out + k, sh, lds, perm);
     }
 }
 
 // ------------------------------------------------------------------ host
 
-size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t)
+size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t,
+                            bool with_w)
 {
     const int elem = dtype == MC_DTYPE_F64 ? 8 : 4;
     size_t best = 0;
     for (int k = 0; k < kTuneBuckets; ++k)
-        best = std::max(best, bat_region_bytes(n_max, t.b[k], elem));
+        best = std::max(best, bat_region_bytes(n_max, t.b[k], elem, with_w));
     return best;
 }
 
