@@ -145,6 +145,22 @@ def householder_qd(n: int, seed: int, reflectors: int, dlo: float = 0.5,
     return a, d, reflectors
 
 
+def gmm(k: int, d: int, m: int, seed: int):
+    """A Gaussian mixture and points to score (the model-mixture use of the
+    Abstract): weights pi ~ U[0.5, 1.5] normalised, means ~ N(0, 4 I),
+    covariances Wishart as above (m = 2d, 2^-12 grid, + 1e-3 I), then m
+    points, each the mean of a component drawn by pi plus N(0, I) noise.
+    Returns (weights (k,), means (k, d), covs: k arrays (d, d), x (m, d))."""
+    g = rng(seed)
+    w = g.uniform(0.5, 1.5, k)
+    w /= w.sum()
+    means = 2.0 * g.standard_normal((k, d))
+    covs = [wishart_from(g, d) for _ in range(k)]
+    comp = g.choice(k, size=m, p=w)
+    x = means[comp] + g.standard_normal((m, d))
+    return w, means, covs, x
+
+
 # Workload table: the five benchmark configurations, by name.
 CONFIGS = {
     "uniform_n1000": dict(kind="uniform", n=1000, seed=1),
@@ -153,6 +169,8 @@ CONFIGS = {
     "wishart_n16384": dict(kind="wishart", n=16384, seed=3),
     "wishart_batch512": dict(kind="wishart_batch", count=512, lo=32, hi=1024, seed=4),
     "wishart_batch64": dict(kind="wishart_batch", count=64, lo=256, hi=2048, seed=5),
+    # mixture log-likelihood: 16 components in 512 dimensions, 16384 points
+    "gmm_k16_d512_m16384": dict(kind="gmm", k=16, d=512, m=16384, seed=6),
 }
 
 
@@ -177,6 +195,8 @@ def make(name: str, **kw):
         return normal(c["n"], c["seed"])
     if kind == "wishart":
         return wishart(c["n"], c["seed"], gram=c.get("gram"))
+    if kind == "gmm":
+        return gmm(c["k"], c["d"], c["m"], c["seed"])
     if kind == "wishart_batch":
         return wishart_batch(c["count"], c["lo"], c["hi"], c["seed"],
                              gram=c.get("gram"))
