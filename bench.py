@@ -402,6 +402,68 @@ def run_batch_grad(args, mc, torch, sizes, mats, devs, allexp, update, stream):
     print(json.dumps(out), flush=True)
 
 
+def run_gmm(args, mc, torch, synth, spec, dev, stream):
+    """Mixture log-likelihood: one step factors the k covariances (one
+    batched factor launch) and scores every point (mc_gmm_loglik)."""
+    import numpy as np
+
+    prec = args.precision if args.precision != "bf16x3" else "f32"
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    print(f"# generating {args.workload}", file=sys.stderr, flush=True)
+    w, means, covs, x = synth.make(args.workload)
+    k, d, m = len(covs), x.shape[1], x.shape[0]
+    cv = [torch.from_numpy(c).to(dev, dtype) for c in covs]
+    xl = torch.from_numpy(x).to(dev, dtype)
+    mu = torch.from_numpy(means).to(dev, dtype)
+    lw = torch.from_numpy(np.log(w)).to(dev)
+
+    def step():
+        fac = mc.gmm_factor(cv)
+        return mc.gmm_loglik(xl, lw, mu, fac)
+
+    steps = args.steps if args.steps is not None else 10
+    warmup = args.warmup if args.warmup is not None else 2
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ll, tot = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # the factor launch alone, for the split
+    e0.record(stream)
+    for _ in range(steps):
+        fac = mc.gmm_factor(cv)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fac = e0.elapsed_time(e1) / steps
+    fac_flops = k * 2.0 * d ** 3 / 3.0
+    solve_flops = k * m * 2.0 * d ** 2
+    peak, _ = mfma_peak(prec)
+    ach = solve_flops / ((ms - ms_fac) * 1e-3) / 1e12
+    out = {
+        "metric": "mixture log-likelihood: points/s (k log-dets + k*m Mahalanobis terms per step)",
+        "value": m / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": args.workload, "k": k, "d": d, "m": m,
+                   "path": "batched factor + mc_gmm_loglik"},
+        "ms_factor": ms_fac, "ms_loglik": ms - ms_fac,
+        "gflops": (fac_flops + solve_flops) / (ms * 1e-3) / 1e9,
+        "total_loglik": float(tot.cpu()),
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None,
+                     "note": "the mixture kernels: 2 d^2 flops per point and component "
+                             "(two triangular substitutions) over the step time minus "
+                             "the factor launch"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args, mc, torch, synth, spec, dev, stream):
     """The batch as one captured graph, replayed: one persistent batched
     launch for the members below BatchedPlan.BLOCKED_MIN_N rows and the
@@ -610,6 +672,9 @@ def main():
     stream = torch.cuda.current_stream(dev)
     if spec["kind"] == "wishart_batch":
         run_batch(args, mc, torch, synth, spec, dev, stream)
+        return
+    if spec["kind"] == "gmm":
+        run_gmm(args, mc, torch, synth, spec, dev, stream)
         return
     n = spec["n"]
     prec = args.precision

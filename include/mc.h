@@ -389,6 +389,43 @@ mc_status mc_logdet_batched_backward(const void* const* LU_array,
                                      size_t work_bytes, void* stream);
 
 /*
+ * Log-likelihood of a Gaussian mixture (the use of the log-determinant the
+ * paper's Abstract names: the log-likelihood of model mixtures), from the
+ * factors of its covariances:
+ *   loglik[i] = log sum_k exp( log_weights[k]
+ *                 - (d log(2 pi) + log|Sigma_k| + q_k(x_i)) / 2 ),
+ *   q_k(x) = (x - mu_k)^T Sigma_k^{-1} (x - mu_k),
+ * with log|Sigma_k| the factor call's result and q_k by two blocked
+ * triangular substitutions per block of 64 points on the kept factors
+ * (Sigma_k^{-1} = Q U^{-1} L^{-1}), block updates on the matrix cores; the
+ * sum over components in FP64, shifted by its largest term.
+ *
+ * X          device, m x d row-major points (row stride ldx >= d).
+ * means      device, k x d row-major (row stride ldmu >= d).
+ * log_weights device, k doubles: log pi_k.
+ * LU_array, ld_array, perm_array  device arrays of k entries: each
+ *            component's factors as mc_logdet_factor or
+ *            mc_logdet_batched_factor leave them (d x d).
+ * fwd        device, the k factor results; a component whose info != 0 or
+ *            whose sign is not +1 (not a covariance) makes every loglik NaN.
+ * dtype      mc_dtype of X, means and the factors (the terms accumulate in
+ *            that type, the sum over components in FP64).
+ * loglik     device, m doubles (output).
+ * total      device, one double: sum_i loglik[i] (output), or NULL.
+ * work       >= mc_gmm_loglik_workspace(m, d, k, dtype) bytes, 256-aligned.
+ * d <= 16384.  Error numbering follows the argument order (X = 1 ...
+ * work = 16).  Graph-capturable (the queue is reset by a kernel).
+ */
+size_t mc_gmm_loglik_workspace(int64_t m, int64_t d, int64_t k, int dtype);
+mc_status mc_gmm_loglik(const void* X, int64_t m, int64_t d, int64_t ldx,
+                        const void* means, int64_t ldmu, int64_t k,
+                        const double* log_weights, const void* const* LU_array,
+                        const int64_t* ld_array,
+                        const int32_t* const* perm_array, const mc_result* fwd,
+                        int dtype, double* loglik, double* total, void* work,
+                        size_t work_bytes, void* stream);
+
+/*
  * The batched path's tuning table: for size buckets n <= 64, 128, 256, 512,
  * 1024 and larger, a panel width b_k (1..128) and a trailing-update tile
  * edge tile_k (32 or 64).  One table per (dtype, update), process-wide,

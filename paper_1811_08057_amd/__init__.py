@@ -45,7 +45,8 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_logdet_backward_recompute", "mc_logdet_rule",
            "mc_logdet_noalloc", "mc_logdet_batched_factor_workspace",
            "mc_logdet_batched_factor", "mc_logdet_batched_backward_workspace",
-           "mc_logdet_batched_backward")
+           "mc_logdet_batched_backward", "mc_gmm_loglik_workspace",
+           "mc_gmm_loglik")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -141,6 +142,11 @@ def lib() -> ctypes.CDLL:
     L.mc_logdet_batched_backward.argtypes = [vp, vp, vp, vp, i64, i64, ci, vp, vp,
                                              vp, vp, vp, sz, vp]
     L.mc_logdet_batched_backward.restype = ci
+    L.mc_gmm_loglik_workspace.argtypes = [i64, i64, i64, ci]
+    L.mc_gmm_loglik_workspace.restype = sz
+    L.mc_gmm_loglik.argtypes = [vp, i64, i64, i64, vp, i64, i64, vp, vp, vp, vp,
+                                vp, ci, vp, vp, vp, sz, vp]
+    L.mc_gmm_loglik.restype = ci
     _lib = L
     return L
 
@@ -693,3 +699,55 @@ def slogdet_batched_autograd(mats, b: int = -1, update="native"):
     """Differentiable (signs, log|det|) of a list of device matrices, as two
     device tensors of len(mats) entries (no host synchronisation)."""
     return MCLogDetBatched.apply(b, update, *mats)
+
+
+# ------------------------------------------------- mixture log-likelihood
+
+class GmmFactors(NamedTuple):
+    """Each component's kept factors (as the factor calls leave them)."""
+    lus: list
+    perms: list
+    fwd: torch.Tensor  # (k, 3) device mc_result structs
+
+
+def gmm_factor(covs, update="native") -> GmmFactors:
+    """Factor the mixture's covariances: one batched factor launch, or the
+    blocked factor call per component from BatchedPlan.BLOCKED_MIN_N rows
+    (the whole-GPU path for large dimensions)."""
+    d = covs[0].shape[0]
+    if d >= BatchedPlan.BLOCKED_MIN_N:
+        outs = [factor(c, update=update) for c in covs]
+        return GmmFactors([o[0] for o in outs], [o[1] for o in outs],
+                          torch.cat([o[2] for o in outs]))
+    lus, perms, res = factor_batched(list(covs), update=update)
+    return GmmFactors(lus, perms, res)
+
+
+def gmm_loglik(x: torch.Tensor, log_weights: torch.Tensor, means: torch.Tensor,
+               fac: GmmFactors, with_total: bool = True):
+    """Per-point log-likelihood (m doubles) and its sum (or None) of a
+    Gaussian mixture from its factored covariances (mc_gmm_loglik).  x: m x d,
+    means: k x d (the factors' dtype); log_weights: k (log pi_k)."""
+    m, d = x.shape
+    k = means.shape[0]
+    dev = x.device
+    if x.stride(1) != 1 or means.stride(1) != 1:
+        raise ValueError("rows must be contiguous")
+    lw = log_weights.detach().to(dev, torch.float64).contiguous()
+    out = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
+    total = torch.empty(1, dtype=torch.float64, device=dev) if with_total else None
+    nb = lib().mc_gmm_loglik_workspace(m, d, k, _dtype_code(x))
+    if nb == 0:
+        raise MCError("unsupported mixture size")
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    lp = _ptr_array(fac.lus, dev)
+    pp = _ptr_array(fac.perms, dev)
+    lds = torch.tensor([_square_rows(u) for u in fac.lus], dtype=torch.int64, device=dev)
+    st = lib().mc_gmm_loglik(
+        x.data_ptr(), m, d, max(x.stride(0), d), means.data_ptr(),
+        max(means.stride(0), d), k, lw.data_ptr(), lp.data_ptr(), lds.data_ptr(),
+        pp.data_ptr(), fac.fwd.data_ptr(), _dtype_code(x), out.data_ptr(),
+        total.data_ptr() if total is not None else None, work.data_ptr(),
+        work.numel(), _stream_ptr(None, dev))
+    _check(st, "mc_gmm_loglik")
+    return out[:m], total

@@ -11,6 +11,7 @@
 #include "mc.h"
 #include "mc_batched.h"
 #include "mc_batched_bwd.h"
+#include "mc_gmm.h"
 #include "mc_internal.h"
 
 namespace mc {
@@ -1052,5 +1053,63 @@ extern "C" mc_status mc_logdet_rule(const void* A, int64_t n, int64_t lda,
     w.piv_col = piv_col;
     const hipError_t e =
         launch_plain_f64(static_cast<const double*>(A), n, lda, w, out, st, rule);
+    return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
+}
+
+// ------------------------------------------------------ mixture log-likelihood
+
+// Largest dimension of the mixture call (the right-hand sides of one work
+// item are kept in the workspace, 64 x d).
+static constexpr int64_t kGmmMaxD = 16384;
+
+extern "C" size_t mc_gmm_loglik_workspace(int64_t m, int64_t d, int64_t k, int dtype)
+{
+    if (m < 0 || d < 1 || d > kGmmMaxD || k < 1 || k > (1 << 20)) return 0;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return 0;
+    return gmm_workspace_bytes(m, d, k, dtype);
+}
+
+extern "C" mc_status mc_gmm_loglik(const void* X, int64_t m, int64_t d, int64_t ldx,
+                                   const void* means, int64_t ldmu, int64_t k,
+                                   const double* log_weights,
+                                   const void* const* LU_array, const int64_t* ld_array,
+                                   const int32_t* const* perm_array,
+                                   const mc_result* fwd, int dtype, double* loglik,
+                                   double* total, void* work, size_t work_bytes,
+                                   void* stream)
+{
+    if (m < 0) return -2;
+    if (m > 0 && X == nullptr) return -1;
+    if (d < 1 || d > kGmmMaxD) return -3;
+    if (ldx < d) return -4;
+    if (means == nullptr) return -5;
+    if (ldmu < d) return -6;
+    if (k < 1 || k > (1 << 20)) return -7;
+    if (log_weights == nullptr) return -8;
+    if (LU_array == nullptr) return -9;
+    if (ld_array == nullptr) return -10;
+    if (perm_array == nullptr) return -11;
+    if (fwd == nullptr) return -12;
+    if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return -13;
+    if (m > 0 && loglik == nullptr) return -14;
+    if (m == 0 && total == nullptr) return MC_OK;  // nothing to write
+    if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -16;
+    if (work_bytes < gmm_workspace_bytes(m, d, k, dtype)) return MC_ERR_WORKSPACE;
+    GmmArgs a{};
+    a.X = X;
+    a.m = m;
+    a.d = d;
+    a.ldx = ldx;
+    a.means = means;
+    a.ldmu = ldmu;
+    a.k = k;
+    a.log_weights = log_weights;
+    a.LU_array = LU_array;
+    a.ld_array = ld_array;
+    a.perm_array = perm_array;
+    a.fwd = fwd;
+    a.loglik = loglik;
+    a.total = total;
+    const hipError_t e = launch_gmm(a, dtype, work, work_bytes, static_cast<hipStream_t>(stream));
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }
