@@ -36,6 +36,12 @@ BF16_PEAK_TFS = 2500.0  # dense MFMA
 # cores over MPI) = 7.17 s.  Another machine's number: context, not a target.
 PAPER_BEST_N8000_S = 7.17
 
+# Round trip of a store by one compute unit to its load by another through
+# one XCD's L2 (sc0|nt loads), measured on MI355X with a probe kernel; a
+# panel step needs at least two (the candidate record, then the winner's
+# column), which sets the floor of the column-split panel chain per step.
+L2_ROUND_TRIP_US = 0.52
+
 # Source file of each timed kernel kind (a stored HBM-traffic measurement is
 # used only while the source it was taken on is unchanged).
 KERNEL_SOURCE = {
@@ -282,6 +288,14 @@ def roofline_of(kind, p, workload, b, prec="f64"):
         r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
     r["traffic"] = stored_traffic(kind, workload, b)
+    if kind == "panel":
+        # the chain is a sequence of dependent steps: its bound is latency
+        steps = b if b > 0 else 1
+        us = avg_us / steps
+        floor = 2.0 * L2_ROUND_TRIP_US
+        r["latency"] = {"steps_per_launch": steps, "us_per_step": us,
+                        "floor_us_per_step": floor, "frac": floor / us,
+                        "floor": "two L2 round trips per step (record, then column)"}
     name = KERNEL_NAME[kind if kind != "update" or prec == "f64"
                        else f"update_{prec}"]
     r.update({"kernel": name, "launches": p.launches,

@@ -1127,18 +1127,28 @@ __device__ __forceinline__ void wave_best_fast(uint64_t& a, uint64_t& k)
     k = readlane64(k, l);
 }
 
-template <typename T, int CPW>
-static size_t split_lds_bytes()
+// Columns per pass of the LDS transposes that load and store a wavefront's
+// columns (at most 32, so the buffer stays 64 x 33 per wavefront).
+template <int CPW>
+constexpr int split_tc()
 {
-    return sizeof(T) * (size_t)kSplitWaves * 64 * (CPW + 1);
+    return CPW < 32 ? CPW : 32;
 }
 
 template <typename T, int CPW>
+static size_t split_lds_bytes()
+{
+    return sizeof(T) * (size_t)kSplitWaves * 64 * (split_tc<CPW>() + 1);
+}
+
+// H: halves of 64 rows the panel has (2 for up to 128 rows, 1 for up to 64).
+template <typename T, int CPW, int H = 2>
 __global__ void __launch_bounds__(kSplitThreads)
 blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, BlkWork<T> w)
 {
     constexpr int CP = kSplitWaves * CPW; // columns per slice
-    constexpr int TBLD = CPW + 1;
+    constexpr int TC = split_tc<CPW>();   // columns per transpose pass
+    constexpr int TBLD = TC + 1;
     extern __shared__ unsigned char smem_raw[];
     T* tb = reinterpret_cast<T*>(smem_raw); // [wave][64][TBLD] transposes
     __shared__ T prow[2][CP];               // row k of the slice, by step parity
@@ -1212,32 +1222,37 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
         invpos[t] = (cl >= 0 && cl < CP && t < width) ? cl : -1;
     }
 
-    // the slice's rows, loaded coalesced and transposed through LDS.  One
-    // buffer descriptor covers the panel rows (rows past nb read as zero);
-    // lane L reads column L % CPW of rows L / CPW + RS u (RS rows a load).
-    constexpr int RS = kWave / CPW;
-    const int c_l = lane % CPW, r_l = lane / CPW;
-    const bool col_ok = cbase + c_l < width;
+    // the slice's rows, loaded coalesced and transposed through LDS, TC
+    // columns a pass.  One buffer descriptor covers the panel rows (rows
+    // past nb read as zero); lane L reads column L % TC of the pass, rows
+    // L / TC + RS u (RS rows a load).
+    constexpr int RS = kWave / TC;
+    const int c_l = lane % TC, r_l = lane / TC;
     const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
         W + (int64_t)s0 * ldw, 0, (int)(sizeof(T) * (int64_t)nb * ldw), 0x00020000);
     const int row_bytes = (int)(sizeof(T) * ldw);
-    T x[2][CPW];
+    T x[H][CPW];
     T* tw = tb + wv * 64 * TBLD;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int voff = r_l * row_bytes + (int)sizeof(T) * (s0 + (col_ok ? cbase + c_l : 0));
-        T t[CPW];
+    for (int h = 0; h < H; ++h) {
 #pragma unroll
-        for (int u = 0; u < CPW; ++u) {
-            const T v = buf_load<T>(prs, voff, (64 * h + RS * u) * row_bytes);
-            t[u] = col_ok ? v : T(0);
+        for (int j = 0; j < CPW / TC; ++j) {
+            const bool col_ok = cbase + j * TC + c_l < width;
+            const int voff = r_l * row_bytes +
+                             (int)sizeof(T) * (s0 + (col_ok ? cbase + j * TC + c_l : 0));
+            T t[TC];
+#pragma unroll
+            for (int u = 0; u < TC; ++u) {
+                const T v = buf_load<T>(prs, voff, (64 * h + RS * u) * row_bytes);
+                t[u] = col_ok ? v : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < TC; ++u) tw[(r_l + RS * u) * TBLD + c_l] = t[u];
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < TC; ++c) x[h][j * TC + c] = tw[lane * TBLD + c];
         }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < CPW; ++u) tw[(r_l + RS * u) * TBLD + c_l] = t[u];
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) x[h][c] = tw[lane * TBLD + c];
     }
 
     const __amdgpu_buffer_rsrc_t stat = l2_rsrc(&w.state->status, sizeof(int));
@@ -1304,14 +1319,16 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
 #pragma unroll
                 for (int c = 0; c < CPW; ++c) {
                     if (B0) y0 = (c == cw) ? x[0][c] : y0;
-                    y1 = (c == cw) ? x[1][c] : y1;
+                    if (H > 1) y1 = (c == cw) ? x[H - 1][c] : y1;
                 }
                 const T r = prow[pb][clw];
                 y0 = fma(-mult[pb][lane], r, y0);
-                y1 = fma(-mult[pb][64 + lane], r, y1);
                 T* col = w.xcol + (size_t)b2 * kMaxPanel;
                 col[lane] = y0;
-                col[64 + lane] = y1;
+                if (H > 1) {
+                    y1 = fma(-mult[pb][64 + lane], r, y1);
+                    col[64 + lane] = y1;
+                }
                 __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
             }
             if (lane == 0) {
@@ -1336,7 +1353,7 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
                 // in scalar registers
                 const T r = wave_uniform(prow[pb][wv * CPW + c]);
                 if (B0) x[0][c] = fma(m0, r, x[0][c]);
-                x[1][c] = fma(m1, r, x[1][c]);
+                if (H > 1) x[H - 1][c] = fma(m1, r, x[H - 1][c]);
             }
             // a use of the updated data here, so that the update stays
             // before the barrier below rather than being moved onto the
@@ -1344,14 +1361,14 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
 #pragma unroll
             for (int c = 0; c < CPW; ++c) {
                 if (B0) asm volatile("" ::"v"(x[0][c]));
-                asm volatile("" ::"v"(x[1][c]));
+                if (H > 1) asm volatile("" ::"v"(x[H - 1][c]));
             }
         }
         // 4. row k+1 (step k-1 now applied) staged for the next step's
         //    candidate by the lane holding it
         if (lane == ((k + 1) & 63)) {
 #pragma unroll
-            for (int c = 0; c < CPW; ++c) nrow[b][wv * CPW + c] = x[HN][c];
+            for (int c = 0; c < CPW; ++c) nrow[b][wv * CPW + c] = x[HN < H ? HN : 0][c];
         }
         // 5. wave 0 takes the winner
         if (wv == 0) {
@@ -1409,7 +1426,8 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
                         sizeof(T) * kMaxPanel);
                     // the column's loads first; the reciprocal of the pivot
                     // and the bookkeeping below overlap them
-                    const T c0 = l2_load<T>(cr, lane), c1 = l2_load<T>(cr, 64 + lane);
+                    const T c0 = l2_load<T>(cr, lane);
+                    const T c1 = H > 1 ? l2_load<T>(cr, 64 + lane) : T(0);
                     const T rp = T(1) / pt;
                     if (lane == 0) {
                         pv[k] = p;
@@ -1479,7 +1497,7 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
     using B_off = std::false_type;
     using H0 = std::integral_constant<int, 0>;
     using H1 = std::integral_constant<int, 1>;
-    const int nbA = nb < 63 ? nb : 63;
+    const int nbA = H > 1 ? (nb < 63 ? nb : 63) : nb;
     // one exit after the loops: a return from inside them would leave the
     // data without a use on that path, and the register allocator then
     // keeps two copies of it alive through every step
@@ -1487,10 +1505,12 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
 #pragma unroll 1
     for (int k = 0; k < nbA && live; ++k)
         live = step(B_on{}, H0{}, k);
-    if (live && nb > 63) live = step(B_on{}, H1{}, 63);
+    if (H > 1) {
+        if (live && nb > 63) live = step(B_on{}, H1{}, 63);
 #pragma unroll 1
-    for (int k = 64; k < nb && live; ++k)
-        live = step(B_off{}, H1{}, k);
+        for (int k = 64; k < nb && live; ++k)
+            live = step(B_off{}, H1{}, k);
+    }
     if (!live) return;
 
     // the factored rows at the columns' final positions (rows past nb fall
@@ -1500,30 +1520,35 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
     // in registers from the loads across the whole step loop.
     int lane_f = lane;
     asm volatile("" : "+v"(lane_f));
-    const int cf_l = lane_f % CPW, rf_l = lane_f / CPW;
-    const int pos_l = cpos[wv * CPW + cf_l];
-    const int soff = rf_l * row_bytes + (int)sizeof(T) * (cbase + cf_l < width ? pos_l : s0);
+    const int cf_l = lane_f % TC, rf_l = lane_f / TC;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < H; ++h) {
         const int i = 64 * h + lane_f;
         const T p = (T)pv[i < nb ? i : 0];
-        __syncthreads();
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            if (c % 4 == 0) __builtin_amdgcn_sched_barrier(0); // a few divisions at a time
-            const T v = h == 0 ? x[0][c] : x[1][c];
-            tw[lane_f * TBLD + c] = (i < cstep[wv * CPW + c]) ? v / p : v;
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        __syncthreads();
-        // rows below a retired column's step hold its multipliers already
-        const int cs_l = cstep[wv * CPW + cf_l];
+        for (int j = 0; j < CPW / TC; ++j) {
+            __syncthreads();
 #pragma unroll
-        for (int u = 0; u < CPW; ++u) {
-            const int r = 64 * h + rf_l + RS * u;
-            if (r <= cs_l)
-                buf_store<T>(tw[(rf_l + RS * u) * TBLD + cf_l], prs, soff,
-                             (64 * h + RS * u) * row_bytes);
+            for (int c = 0; c < TC; ++c) {
+                if (c % 4 == 0) __builtin_amdgcn_sched_barrier(0); // a few divisions at a time
+                const T v = x[h][j * TC + c];
+                tw[lane_f * TBLD + c] = (i < cstep[wv * CPW + j * TC + c]) ? v / p : v;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
+            // rows below a retired column's step hold its multipliers already
+            const int colj = wv * CPW + j * TC + cf_l;
+            const int pos_l = cpos[colj];
+            const int soff = rf_l * row_bytes +
+                             (int)sizeof(T) * (cbase + j * TC + cf_l < width ? pos_l : s0);
+            const int cs_l = cstep[colj];
+#pragma unroll
+            for (int u = 0; u < TC; ++u) {
+                const int r = 64 * h + rf_l + RS * u;
+                if (r <= cs_l)
+                    buf_store<T>(tw[(rf_l + RS * u) * TBLD + cf_l], prs, soff,
+                                 (64 * h + RS * u) * row_bytes);
+            }
         }
     }
     for (int t = tid; t < CP; t += kSplitThreads)
@@ -1626,14 +1651,14 @@ static bool try_panel_x(int64_t n, int64_t s0, int64_t pend,
     return true;
 }
 
-template <typename T, int CPW>
+template <typename T, int CPW, int H = 2>
 static hipError_t launch_split(int64_t n, int64_t s0, int nb, const BlkWork<T>& w,
                                hipStream_t stream, bool on_xcc0)
 {
     static bool attr_set = false; // guarded by g_sched_mu (held by the caller)
     if (!attr_set) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&blk_panel_split<T, CPW>),
+            reinterpret_cast<const void*>(&blk_panel_split<T, CPW, H>),
             hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes<T, CPW>());
         if (e != hipSuccess) return note_hip_error(e);
         attr_set = true;
@@ -1641,16 +1666,30 @@ static hipError_t launch_split(int64_t n, int64_t s0, int nb, const BlkWork<T>& 
     constexpr int CP = kSplitWaves * CPW;
     const int slices = (int)((n - s0 + CP - 1) / CP);
     const size_t lds = split_lds_bytes<T, CPW>();
-    hipLaunchKernelGGL((blk_panel_split<T, CPW>), dim3((unsigned)(8 * slices)),
+    hipLaunchKernelGGL((blk_panel_split<T, CPW, H>), dim3((unsigned)(8 * slices)),
                        dim3(kSplitThreads), lds, stream, n, s0, nb, slices,
                        on_xcc0 ? 1 : 0, w);
     return hipSuccess;
 }
 
-// `on`: the column-split setting, read once per call.
-static bool split_fits(int64_t width, bool on)
+// Most columns per wavefront of the column-split panel for a panel of nb
+// rows: each lane holds ceil(nb / 64) x CPW values in registers, at most
+// 128 of them -- 64 columns for FP32, or for FP64 panels of at most 64 rows,
+// else 32 -- so one XCD's slices span up to 16384 columns (8192 for FP64
+// panels of more than 64 rows).
+template <typename T>
+constexpr int split_cpw_max(int nb)
 {
-    return on && width <= (int64_t)kSplitSlices * kSplitWaves * 32;
+    return (sizeof(T) == 4 || nb <= 64) ? 64 : 32;
+}
+
+// `on`: the column-split setting, read once per call; `beside`: the panel
+// runs beside a trailing update and keeps one compute unit of its XCD free.
+template <typename T>
+static bool split_fits(int64_t width, int nb, bool on, bool beside = false)
+{
+    const int64_t slices = beside ? kSplitSlices - 1 : kSplitSlices;
+    return on && width <= slices * kSplitWaves * split_cpw_max<T>(nb);
 }
 
 // The column-split panel for a panel of width n - s0 (split_fits): the
@@ -1670,7 +1709,14 @@ static hipError_t launch_panel_split(int64_t n, int64_t s0, int nb,
         return launch_split<T, 8>(n, s0, nb, w, stream, on_xcc0);
     if (width <= slices * kSplitWaves * 16)
         return launch_split<T, 16>(n, s0, nb, w, stream, on_xcc0);
-    return launch_split<T, 32>(n, s0, nb, w, stream, on_xcc0);
+    if (width <= slices * kSplitWaves * 32)
+        return launch_split<T, 32>(n, s0, nb, w, stream, on_xcc0);
+    // wider (split_fits): 64 columns per wavefront, the panel's 128 rows in
+    // FP32, at most 64 rows in FP64
+    if constexpr (sizeof(T) == 4)
+        return launch_split<T, 64, 2>(n, s0, nb, w, stream, on_xcc0);
+    else
+        return launch_split<T, 64, 1>(n, s0, nb, w, stream, on_xcc0);
 }
 
 template <typename T>
@@ -2258,13 +2304,29 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     DevSched* la = lookahead ? ds : nullptr;
     bool pending = false; // side-stream work the caller's stream must join
     bool beside = false;  // ... and it leaves XCD 0 to the next panel
-    for (int64_t s0 = 0, k = 0; s0 < n; s0 += b, ++k) {
-        const int nb = (int)std::min<int64_t>(b, n - s0);
+    // rows of the panel starting at s0: b, except that FP64 panels wider
+    // than one XCD holds at 32 columns per wavefront (8192) take at most 64
+    // rows, so that the column-split panel holds 64 columns per wavefront
+    // (up to 16384) instead of falling back to the row-per-block chain
+    auto panel_rows = [&](int64_t s0) -> int {
+        int64_t nb = std::min<int64_t>(b, n - s0);
+        if (sizeof(T) == 8 && !split_fits<T>(n - s0, (int)nb, split_on) &&
+            split_fits<T>(n - s0, 64, split_on))
+            nb = std::min<int64_t>(nb, 64);
+        return (int)nb;
+    };
+    int64_t last_s0 = 0, last_k = 0;
+    int last_nb = 0;
+    for (int64_t s0 = 0, k = 0; s0 < n; ++k) {
+        const int nb = panel_rows(s0);
         const int64_t pend = s0 + nb;
+        last_s0 = s0;
+        last_nb = nb;
+        last_k = k;
         // the panel chains need their blocks resident together on one XCD:
         // the one block 0 lands on, or XCD 0 when the trailing update
         // running beside the panel (lookahead) leaves that XCD alone
-        const bool split = split_fits(n - s0, split_on);
+        const bool split = split_fits<T>(n - s0, nb, split_on);
         if (!split) launch_head<T>(n, s0, w, stream);
         const int ept = step_ept(n - s0);
         const bool persistent = !split && ept > 0 && nb > 1;
@@ -2328,8 +2390,10 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         // panel's TRSM or blk_perm).  Otherwise one launch for all rows:
         // beside a row-per-block panel chain the update's tiles would share
         // its XCD and slow it more than the overlap gains.
-        beside = la && la->all_xccs && split_fits(n - pend, split_on) && rows > b;
-        const int64_t next = beside ? b : rows;
+        const int next_nb = panel_rows(pend);
+        beside = la && la->all_xccs && split_fits<T>(n - pend, next_nb, split_on, true) &&
+                 rows > next_nb;
+        const int64_t next = beside ? next_nb : rows;
         hipError_t e = trailing(wk, update, s0, nb, pend, next, n, stream, nullptr);
         if (e != hipSuccess) return e;
         hipStream_t rest = stream;
@@ -2354,6 +2418,7 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
             if ((e = hipEventRecord(la->join, rest)) != hipSuccess) return note_hip_error(e);
             pending = true;
         }
+        s0 = pend;
     }
     if (pending) {
         const hipError_t e = hipStreamWaitEvent(stream, la->join, 0);
@@ -2362,10 +2427,10 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     // the last panel (no rows below): its exchanges still reach the rows
     // above it in factor mode
     if (factor && n > 0) {
-        const int64_t s0 = ((n - 1) / b) * b;
-        const int nb = (int)(n - s0);
+        const int64_t s0 = last_s0;
+        const int nb = last_nb;
         if (s0 > 0) {
-            const BlkWork<T> wk = panel_view(w, s0 / b);
+            const BlkWork<T> wk = panel_view(w, last_k);
             hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
                                s0, nb, wk);
             hipLaunchKernelGGL(blk_swaps_above<T>, dim3((unsigned)((s0 + 3) / 4)),

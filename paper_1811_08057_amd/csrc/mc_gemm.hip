@@ -69,14 +69,13 @@ __device__ __forceinline__ void counter_tiles(const GemmArgs<T>& g, int bm, int 
 // 27.4 against 22.9 on the seven XCDs beside a panel chain.  In FP32 the
 // same 16 wavefronts fit twice per compute unit without C (49 VGPRs), which
 // is faster still: 65.7 against 56.0 TFLOP/s with C and 51.2 for 8.
-template <class P, int WGM, int WGN, int TM, int TN, bool PF>
+template <class P, int WGM, int WGN, int TM, int TN, bool PF, int KC = 16>
 __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
                                             int64_t rb, int64_t cb, int tid)
 {
     using T = typename P::T;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int BM = 16 * TM * WGM, BN = 16 * TN * WGN;
-    constexpr int KC = 16;
     constexpr int LDA = BM + 16, LDB = BN + 16; // conflict-free fragment reads
     constexpr int PA = (BM * KC + NT - 1) / NT, PB = (BN * KC + NT - 1) / NT;
     __shared__ T As[2][KC][LDA]; // -L, transposed (k major)
@@ -204,17 +203,17 @@ __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
 // next tile may refill the buffers at once.
 // WPS: wavefronts per SIMD the launch bound asks for (the register budget:
 // 512 / WPS VGPRs); PF: the old C read inside the K loop.
-template <class P, int WGM, int WGN, int TM, int TN, int WPS, bool PF>
+template <class P, int WGM, int WGN, int TM, int TN, int WPS, bool PF, int KC = 16>
 __global__ void __launch_bounds__(64 * WGM * WGN, WPS)
 gemm_scalar(GemmArgs<typename P::T> g)
 {
     if (g.state->status != kStatusOk) return;
     constexpr int BM = 16 * TM * WGM, BN = 16 * TN * WGN;
-    scalar_tile<P, WGM, WGN, TM, TN, PF>(g, (int64_t)blockIdx.y * BM, (int64_t)blockIdx.x * BN,
-                                         (int)threadIdx.x);
+    scalar_tile<P, WGM, WGN, TM, TN, PF, KC>(g, (int64_t)blockIdx.y * BM,
+                                             (int64_t)blockIdx.x * BN, (int)threadIdx.x);
 }
 
-template <class P, int WGM, int WGN, int TM, int TN, int WPS, bool PF>
+template <class P, int WGM, int WGN, int TM, int TN, int WPS, bool PF, int KC = 16>
 __global__ void __launch_bounds__(64 * WGM * WGN, WPS)
 gemm_scalar_spare(GemmArgs<typename P::T> g)
 {
@@ -226,7 +225,7 @@ gemm_scalar_spare(GemmArgs<typename P::T> g)
         // derived from it would hold registers through the K loop
         int tid = (int)threadIdx.x;
         asm volatile("" : "+v"(tid));
-        scalar_tile<P, WGM, WGN, TM, TN, PF>(g, rb, cb, tid);
+        scalar_tile<P, WGM, WGN, TM, TN, PF, KC>(g, rb, cb, tid);
     });
 }
 

@@ -344,3 +344,52 @@ def test_wishart_n16384_expected(wishart_n16384, precision, update):
     print(f"[blocked] wishart_n16384 {precision}/{update}: rel err "
           f"{rel(got, ref):.3e} (vs FP64 oracle on FP64 input "
           f"{abs(got.logabsdet - e64) / abs(e64):.3e})")
+
+
+@pytest.mark.parametrize("precision,update", [("f64", "native"),
+                                              ("f32", "f32"),
+                                              ("f32", "bf16x3")])
+def test_wishart_n16384_pivot_sequence(wishart_n16384, precision, update):
+    """The whole pivot sequence of the N = 16384 Wishart input against the
+    FP64 oracle's (stored): every pivot of this covariance beats its
+    runner-up by at least 96% relative (min_gap), far beyond any FP32
+    rounding difference, so all 16384 steps must match -- on FP32 storage
+    too, where the first panels (wider than 8192 columns) run on the
+    64-column-per-wavefront column-split panel."""
+    with open(os.path.join(GOLDEN, "expected_wishart_n16384.json")) as f:
+        exp = json.load(f)
+    assert exp["f64"]["gap_safe_steps"] == 16384 and exp["f64"]["min_gap"] > 0.5
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    print(f"[blocked] wishart_n16384 pivots {precision}/{update}", flush=True)
+    a = torch.from_numpy(wishart_n16384).to(DEV, dtype)
+    r, piv = mc.slogdet_pivots(a, b=-1, update=update)
+    assert r.info == 0
+    assert np.array_equal(piv.cpu().numpy(), np.array(exp["f64"]["piv_col"]))
+
+
+@pytest.mark.parametrize("dtype,update", [(torch.float64, "native"),
+                                          (torch.float32, "f32")])
+def test_wide_panels_closed_form_and_factors(dtype, update):
+    """n = 8704: the first panels are wider than 8192 columns -- FP64 takes
+    64-row panels on the 64-column-per-wavefront column-split kernel, FP32
+    128-row panels on it -- then the usual 128-row panels.  log|det| and
+    the sign against the closed form of Q diag(d) (Q a product of
+    Householder reflectors), and the factor call's L U against A[:, perm]."""
+    n = 8704
+    a, d, r_ = synth.householder_qd(n, 5, 4)
+    ref = float(np.sum(np.log(np.abs(d))))
+    sign = (-1) ** r_ * np.prod(np.sign(d))
+    print(f"[blocked] wide panels n={n} {dtype} {update}", flush=True)
+    at = torch.from_numpy(a).to(DEV, dtype)
+    got = mc.slogdet(at, b=-1, update=update)
+    tol = TOL64 if dtype == torch.float64 else TOL_MIXED
+    assert got.info == 0 and got.sign == sign
+    assert abs(got.logabsdet - ref) <= tol * max(abs(ref), 1.0)
+    if dtype == torch.float64:
+        lu, perm, res = mc.factor(at, b=-1)
+        r = mc.read_result(res)[0]
+        assert r.sign == sign and abs(r.logabsdet - ref) <= tol * abs(ref)
+        L = torch.tril(lu)
+        U = torch.triu(lu, 1) + torch.eye(n, dtype=lu.dtype, device=DEV)
+        err = float((at[:, perm.long()] - L @ U).abs().max())
+        assert err <= 1e-11 * n * float(at.abs().max()), err
