@@ -88,6 +88,9 @@ def parse():
                         "three times (the reference kernel for scaling the "
                         "HBM counters FETCH_SIZE / WRITE_SIZE)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-tune", action="store_true",
+                   help="batch workloads: keep the library's default tuning "
+                        "table instead of the autotuned one (cached per device)")
     p.add_argument("--grad", action="store_true",
                    help="batch workloads: time forward + backward (one "
                         "batched factor launch, the blocked factor call for "
@@ -493,6 +496,16 @@ def run_batch(args, mc, torch, synth, spec, dev, stream):
     if prec != "f64":
         check_input(allexp, "sha256_f32", [m.astype("float32") for m in mats])
     devs = [torch.from_numpy(m).to(dev, dtype) for m in mats]
+    tune = None
+    if not args.no_tune:
+        # the panel widths and tiles of the batched launch from the
+        # library's autotuner (cached per device), up to the largest member
+        # the batched launch takes
+        small_max = max([n for n in sizes if n < mc.BatchedPlan.BLOCKED_MIN_N], default=0)
+        if small_max > 0:
+            print("# autotuning the batched path", file=sys.stderr, flush=True)
+            tb, tt, src = mc.autotune_cached(dtype, update, min(small_max, 4096), dev)
+            tune = {"b": tb, "tile": tt, "source": src}
     if args.grad:
         run_batch_grad(args, mc, torch, sizes, mats, devs, allexp, update, stream)
         return
@@ -540,7 +553,8 @@ def run_batch(args, mc, torch, synth, spec, dev, stream):
         "config": {"workload": args.workload, "batch": len(sizes),
                    "n_min": min(sizes), "n_max": max(sizes),
                    "precision": prec, "path": "batched", "graph": True,
-                   "blocked_members": len(plan.large)},
+                   "blocked_members": len(plan.large),
+                   "tune": tune or "library defaults"},
         "gflops": flops / (ms * 1e-3) / 1e9,
         "rel_err_vs_oracle": worst, "sign_matches_oracle": signs,
         "roofline": roof,
@@ -721,10 +735,12 @@ def main():
           file=sys.stderr, flush=True)
     ms_per_step, got, _ = timed(mc, torch, a, b, steps, warmup, stream,
                                 update=update)
-    print(f"# kernel timing pass: {args.profile_steps} steps",
-          file=sys.stderr, flush=True)
-    prof_ms, _, prof = timed(mc, torch, a, b, args.profile_steps, 0, stream,
-                             profile=True, update=update)
+    prof_ms, prof = None, None
+    if args.profile_steps > 0:  # 0: no kernel-timing pass (counter runs)
+        print(f"# kernel timing pass: {args.profile_steps} steps",
+              file=sys.stderr, flush=True)
+        prof_ms, _, prof = timed(mc, torch, a, b, args.profile_steps, 0, stream,
+                                 profile=True, update=update)
     value = 1000.0 / ms_per_step
     gflops = (2.0 * n ** 3 / 3.0) / (ms_per_step * 1e-3) / 1e9
 
@@ -743,15 +759,17 @@ def main():
 
     # roofline of the dominant kernel (largest timed share of the step)
     entries = {}
-    for k in (["plain_step"] if plain else ["panel", "update"]):
+    for k in (["plain_step"] if plain else ["panel", "update"]) if prof else []:
         p = prof["update" if k == "plain_step" else k]
         r = roofline_of(k, p, args.workload, b, prec)
         if r is not None:
             r["share_of_step"] = p.elapsed_ms / args.profile_steps / prof_ms
             r["timing_pass_ms_per_step"] = prof_ms
             entries[k] = r
-    dominant = max(entries, key=lambda k: entries[k]["share_of_step"])
-    roof = dict(entries[dominant])
+    roof = None
+    if entries:
+        dominant = max(entries, key=lambda k: entries[k]["share_of_step"])
+        roof = dict(entries[dominant])
 
     out = {
         "metric": METRIC, "value": value, "unit": "log-dets/s",

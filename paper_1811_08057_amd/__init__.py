@@ -538,6 +538,88 @@ def autotune_batched(dtype=torch.float64, update="native", n_max: int = 1024,
     return tune_get(dtype, update)
 
 
+def _tune_key(dtype, update, n_max: int, device) -> str:
+    props = torch.cuda.get_device_properties(device)
+    arch = getattr(props, "gcnArchName", "")
+    return (f"{props.name}|{arch}|cu{props.multi_processor_count}|"
+            f"v{lib().mc_version()}|{'f64' if _dtype_of(dtype) == DTYPE_F64 else 'f32'}|"
+            f"u{_update_code(update)}|n{n_max}")
+
+
+def default_tune_cache() -> str:
+    base = os.environ.get("MC_TUNE_CACHE")
+    if base:
+        return base
+    return os.path.join(os.path.expanduser("~"), ".cache", "paper_1811_08057_amd",
+                        "tune.json")
+
+
+def load_tune_entry(path: str, key: str):
+    """(b list, tile list) stored under `key` in the cache file, or None when
+    the file is missing, unreadable or holds no valid entry for the key."""
+    import json
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        e = data[key]
+        b, t = [int(x) for x in e["b"]], [int(x) for x in e["tile"]]
+        if len(b) != len(TUNE_BUCKETS) or len(t) != len(TUNE_BUCKETS):
+            return None
+        return b, t
+    except (OSError, ValueError, KeyError, TypeError):
+        return None
+
+
+def store_tune_entry(path: str, key: str, b, tile) -> bool:
+    """Add or replace one entry of the cache file (written atomically)."""
+    import json
+    try:
+        data = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                data = json.load(f)
+            if not isinstance(data, dict):
+                data = {}
+    except (OSError, ValueError):
+        data = {}
+    data[key] = {"b": list(b), "tile": list(tile)}
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1)
+        os.replace(tmp, path)
+        return True
+    except OSError:
+        return False
+
+
+def autotune_cached(dtype=torch.float64, update="native", n_max: int = 1024,
+                    device=None, cache: Optional[str] = None):
+    """The batched path's tuning table for this device, set in the library
+    and returned with where it came from ("cache", "tuned" or "default"):
+    the cache file's entry for this device, library version, dtype, update
+    and n_max when there is one; else mc_autotune_batched now, stored in
+    the cache; the library's defaults if tuning fails."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    path = cache or default_tune_cache()
+    key = _tune_key(dtype, update, n_max, device)
+    hit = load_tune_entry(path, key)
+    if hit is not None:
+        try:
+            tune_set(hit[0], hit[1], dtype, update)
+            return hit[0], hit[1], "cache"
+        except MCError:
+            pass  # an entry the library rejects: tune afresh
+    try:
+        b, t = autotune_batched(dtype, update, n_max, device)
+    except (MCError, RuntimeError):
+        b, t = tune_get(dtype, update)
+        return b, t, "default"
+    store_tune_entry(path, key, b, t)
+    return b, t, "tuned"
+
+
 # ------------------------------------------------------- factor / backward
 
 def factor(a: torch.Tensor, b: int = -1, update="native"):

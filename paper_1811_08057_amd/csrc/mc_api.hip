@@ -501,7 +501,7 @@ extern "C" size_t mc_logdet_batched_backward_workspace(int64_t batch, int64_t n_
 {
     if (batch < 0 || n_max < 0 || n_max > kBatchedBwdMaxN) return 0;
     if (dtype != MC_DTYPE_F64 && dtype != MC_DTYPE_F32) return 0;
-    return batched_bwd_workspace_bytes(batch, n_max);
+    return batched_bwd_workspace_bytes(batch, n_max, dtype);
 }
 
 extern "C" mc_status mc_logdet_batched_backward(
@@ -521,7 +521,7 @@ extern "C" mc_status mc_logdet_batched_backward(
     if (batch > 0 && ldg_array == nullptr) return -11;
     if (batch == 0) return MC_OK;
     if (work == nullptr || reinterpret_cast<uintptr_t>(work) % 256 != 0) return -12;
-    if (work_bytes < batched_bwd_workspace_bytes(batch, n_max)) return MC_ERR_WORKSPACE;
+    if (work_bytes < batched_bwd_workspace_bytes(batch, n_max, dtype)) return MC_ERR_WORKSPACE;
     BatchedBwdArgs a{};
     a.LU_array = LU_array;
     a.n_array = n_array;

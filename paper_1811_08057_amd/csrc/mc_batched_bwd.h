@@ -23,11 +23,13 @@ struct BatchedBwdArgs {
     const int64_t* ldg_array;       // device
     int* counter;                   // [0] queue head, [1] item count
     int* items;                     // (matrix, column block) pairs
+    void* inv;                      // per matrix: its diagonal blocks' inverses
+    size_t inv_stride;              // bytes between two matrices' inverses
     size_t lds_elems;               // dynamic LDS of the launch, in elements
 };
 
 size_t batched_bwd_lds_bytes(int dtype, int64_t n_max);
-size_t batched_bwd_workspace_bytes(int64_t batch, int64_t n_max);
+size_t batched_bwd_workspace_bytes(int64_t batch, int64_t n_max, int dtype);
 hipError_t launch_batched_backward(BatchedBwdArgs a, int dtype, void* work,
                                    hipStream_t stream);
 

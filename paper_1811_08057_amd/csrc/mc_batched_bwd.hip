@@ -113,8 +113,10 @@ __device__ void bbwd_item(const BatchedBwdArgs& a, int k, int J, T* lds)
     T* Bs = As + kQW * kQLD;       // [64][kQLD]
     T* D = As;                     // [64][kQXLD] diagonal block (aliases As, Bs)
 
+    const T* inv = reinterpret_cast<const T*>(static_cast<const unsigned char*>(a.inv) +
+                                              (size_t)k * a.inv_stride);
     // Y = U^{-1} L^{-1} E_J; L^{-1} E_J is zero above block J
-    lu_solve_rhs<T>(LU, ld, n, Yt, ldg, w, J, true, X, As, Bs, D);
+    lu_solve_rhs<T>(LU, ld, n, inv, Yt, ldg, w, J, true, X, As, Bs, D);
     // G[c0 + j][perm[s]] = g Y[s][j]: each row through LDS, then scattered
     const int32_t* perm = a.perm_array[k];
     T* buf = lds;
@@ -135,6 +137,25 @@ __device__ void bbwd_item(const BatchedBwdArgs& a, int k, int J, T* lds)
         }
         __syncthreads();
     }
+}
+
+// The diagonal blocks' inverses of every member: block (2 B + half, k).
+template <typename T>
+__global__ void __launch_bounds__(kQB)
+bbwd_invert(BatchedBwdArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int64_t per = 2 * qblocks(std::max<int64_t>(a.n_max, 1));
+    const int k = (int)(blockIdx.x / per);
+    const int64_t half = blockIdx.x - (int64_t)k * per;
+    const int64_t B = half >> 1;
+    const int64_t n = a.n_array[k];
+    if (n < 0 || n > a.n_max || B >= qblocks(n)) return;
+    if (a.fwd != nullptr && a.fwd[k].info != 0) return; // no valid factors
+    T* inv = reinterpret_cast<T*>(static_cast<unsigned char*>(a.inv) + (size_t)k * a.inv_stride);
+    invert_diag_block<T>(static_cast<const T*>(a.LU_array[k]), a.ld_array[k], n, B,
+                         (half & 1) != 0, inv, lds, lds + kQW * kQXLD);
 }
 
 template <typename T>
@@ -166,12 +187,19 @@ size_t batched_bwd_lds_bytes(int dtype, int64_t n_max)
     return std::max(solve, row);
 }
 
-size_t batched_bwd_workspace_bytes(int64_t batch, int64_t n_max)
+static size_t inv_stride_bytes(int64_t n_max, size_t elem)
 {
+    return align_up(elem * 2 * kQW * kQW * (size_t)qblocks(std::max<int64_t>(n_max, 1)), 256);
+}
+
+size_t batched_bwd_workspace_bytes(int64_t batch, int64_t n_max, int dtype)
+{
+    const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
     const int64_t items = std::max<int64_t>(batch, 1) * qblocks(std::max<int64_t>(n_max, 1));
     return align_up(sizeof(int) * 64, 256) +
            align_up(sizeof(int) * (size_t)std::max<int64_t>(batch, 1), 256) +
-           align_up(sizeof(int) * 2 * (size_t)items, 256);
+           align_up(sizeof(int) * 2 * (size_t)items, 256) +
+           (size_t)std::max<int64_t>(batch, 1) * inv_stride_bytes(n_max, elem);
 }
 
 hipError_t launch_batched_backward(BatchedBwdArgs a, int dtype, void* work,
@@ -183,10 +211,29 @@ hipError_t launch_batched_backward(BatchedBwdArgs a, int dtype, void* work,
     int* order = reinterpret_cast<int*>(p);
     p += align_up(sizeof(int) * (size_t)std::max<int64_t>(a.batch, 1), 256);
     a.items = reinterpret_cast<int*>(p);
+    const int64_t items_max = std::max<int64_t>(a.batch, 1) * qblocks(std::max<int64_t>(a.n_max, 1));
+    p += align_up(sizeof(int) * 2 * (size_t)items_max, 256);
+    a.inv = p;
+    a.inv_stride = inv_stride_bytes(a.n_max, dtype == MC_DTYPE_F64 ? 8 : 4);
     const size_t lds = batched_bwd_lds_bytes(dtype, a.n_max);
     a.lds_elems = lds / (dtype == MC_DTYPE_F64 ? 8 : 4);
     hipLaunchKernelGGL(bbwd_setup, dim3(1), dim3(kQB), 0, stream, a.n_array, a.batch,
                        a.n_max, a.counter, order, a.items);
+    {
+        const size_t inv_lds = (dtype == MC_DTYPE_F64 ? 8 : 4) * (size_t)(2 * kQW * kQXLD);
+        const void* fi = dtype == MC_DTYPE_F64 ? reinterpret_cast<const void*>(&bbwd_invert<double>)
+                                               : reinterpret_cast<const void*>(&bbwd_invert<float>);
+        if (inv_lds > 64 * 1024) {
+            const hipError_t ea = hipFuncSetAttribute(fi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      (int)inv_lds);
+            if (ea != hipSuccess) return note_hip_error(ea);
+        }
+        const dim3 ig((unsigned)(2 * qblocks(std::max<int64_t>(a.n_max, 1)) * a.batch));
+        if (dtype == MC_DTYPE_F64)
+            hipLaunchKernelGGL(bbwd_invert<double>, ig, dim3(kQB), inv_lds, stream, a);
+        else
+            hipLaunchKernelGGL(bbwd_invert<float>, ig, dim3(kQB), inv_lds, stream, a);
+    }
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return note_hip_error(e);

@@ -28,6 +28,8 @@ struct GmmArgs {
     double* partial; // per-block sums of loglik
     void* slots;     // per workgroup: 64 right-hand sides of ldy elements
     int64_t ldy;
+    void* inv;       // per component: its diagonal blocks' inverses
+    size_t inv_stride;
 };
 
 int64_t gmm_ldy(int64_t d);

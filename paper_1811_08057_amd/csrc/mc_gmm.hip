@@ -60,7 +60,9 @@ __device__ void gmm_item(const GmmArgs& a, int k, int P0, T* lds, T* slot)
     T* Xl = lds;
     T* As = Xl + kQW * kQXLD;
     T* Bs = As + kQW * kQLD;
-    lu_solve_rhs<T>(LU, ld, d, slot, ldy, w, 0, false, Xl, As, Bs, As);
+    const T* inv = reinterpret_cast<const T*>(static_cast<const unsigned char*>(a.inv) +
+                                              (size_t)k * a.inv_stride);
+    lu_solve_rhs<T>(LU, ld, d, inv, slot, ldy, w, 0, false, Xl, As, Bs, As);
     // q_j = sum_s r_j[perm[s]] y_j[s]: each wavefront takes 16 points
     for (int j = wv; j < w; j += kQB / kWave) {
         const T* rx = X + (p0 + j) * a.ldx;
@@ -98,6 +100,23 @@ gmm_items(GmmArgs a)
 }
 
 __global__ void gmm_reset(int* counter) { *counter = 0; }
+
+// The diagonal blocks' inverses of every component (one workgroup per
+// block and half; components that are not covariances are skipped).
+template <typename T>
+__global__ void __launch_bounds__(kQB)
+gmm_invert(GmmArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int64_t per = 2 * qblocks(a.d);
+    const int64_t k = blockIdx.x / per, half = blockIdx.x - k * per;
+    const mc_result* f = a.fwd + k;
+    if (f->info != 0 || !(f->sign > 0.0)) return;
+    T* inv = reinterpret_cast<T*>(static_cast<unsigned char*>(a.inv) + (size_t)k * a.inv_stride);
+    invert_diag_block<T>(static_cast<const T*>(a.LU_array[k]), a.ld_array[k], a.d, half >> 1,
+                         (half & 1) != 0, inv, lds, lds + kQW * kQXLD);
+}
 
 // l(x_i) from the Mahalanobis terms, one thread per point; per-block sums
 // for the total.
@@ -165,6 +184,11 @@ int64_t gmm_grid(int64_t items)
 
 int64_t gmm_ldy(int64_t d) { return (d + 15) / 16 * 16; }
 
+static size_t gmm_inv_stride(int64_t d, size_t elem)
+{
+    return align_up(elem * 2 * kQW * kQW * (size_t)qblocks(d), 256);
+}
+
 size_t gmm_workspace_bytes(int64_t m, int64_t d, int64_t k, int dtype)
 {
     const size_t elem = dtype == MC_DTYPE_F64 ? 8 : 4;
@@ -175,7 +199,8 @@ size_t gmm_workspace_bytes(int64_t m, int64_t d, int64_t k, int dtype)
     return align_up(sizeof(int) * 64, 256) +
            align_up(sizeof(double) * (size_t)std::max<int64_t>(m * k, 1), 256) +
            align_up(sizeof(double) * (size_t)std::max<int64_t>(pblocks, 1), 256) +
-           align_up(elem * (size_t)slots * kQW * (size_t)gmm_ldy(d), 256);
+           align_up(elem * (size_t)slots * kQW * (size_t)gmm_ldy(d), 256) +
+           (size_t)k * gmm_inv_stride(d, elem);
 }
 
 hipError_t launch_gmm(GmmArgs a, int dtype, void* work, size_t work_bytes,
@@ -193,10 +218,29 @@ hipError_t launch_gmm(GmmArgs a, int dtype, void* work, size_t work_bytes,
     p += align_up(sizeof(double) * (size_t)std::max<int64_t>(pblocks, 1), 256);
     a.slots = p;
     a.ldy = gmm_ldy(a.d);
+    const int64_t nslots = std::min<int64_t>(2 * 256, std::max<int64_t>(qblocks(a.m) * a.k, 1));
+    p += align_up(elem * (size_t)nslots * kQW * (size_t)a.ldy, 256);
+    a.inv = p;
+    a.inv_stride = gmm_inv_stride(a.d, elem);
     const int64_t items = qblocks(a.m) * a.k;
     const int64_t grid = std::min<int64_t>(gmm_grid(items), 2 * 256);
     const size_t lds = elem * (size_t)(kQW * kQXLD + 2 * kQW * kQLD);
     hipLaunchKernelGGL(gmm_reset, dim3(1), dim3(1), 0, stream, a.counter);
+    {
+        const size_t inv_lds = elem * (size_t)(2 * kQW * kQXLD);
+        const void* fi = dtype == MC_DTYPE_F64 ? reinterpret_cast<const void*>(&gmm_invert<double>)
+                                               : reinterpret_cast<const void*>(&gmm_invert<float>);
+        if (inv_lds > 64 * 1024) {
+            const hipError_t e = hipFuncSetAttribute(fi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)inv_lds);
+            if (e != hipSuccess) return note_hip_error(e);
+        }
+        const dim3 ig((unsigned)(2 * qblocks(a.d) * a.k));
+        if (dtype == MC_DTYPE_F64)
+            hipLaunchKernelGGL(gmm_invert<double>, ig, dim3(kQB), inv_lds, stream, a);
+        else
+            hipLaunchKernelGGL(gmm_invert<float>, ig, dim3(kQB), inv_lds, stream, a);
+    }
     const void* f = dtype == MC_DTYPE_F64 ? reinterpret_cast<const void*>(&gmm_items<double>)
                                           : reinterpret_cast<const void*>(&gmm_items<float>);
     if (lds > 64 * 1024) {

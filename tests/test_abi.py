@@ -97,3 +97,30 @@ def test_rule_call_argument_checks():
     assert lib.mc_logdet_rule(fake, 4, 4, 2, piv, None, fake, 1 << 20, None) == -6
     assert lib.mc_logdet_rule(fake, 4, 4, 1, None, out, None, 1 << 20, None) == -7
     assert lib.mc_logdet_rule(fake, 4, 4, 1, None, out, fake, 16, None) == -100
+
+
+def test_tune_cache_round_trip_and_fallbacks(tmp_path):
+    """The tuning-table cache (host side only): an entry stored is read back
+    and set in the library; a corrupt file or a malformed entry reads as
+    missing (the caller then tunes, or keeps the defaults)."""
+    path = str(tmp_path / "tune.json")
+    b = [16, 32, 32, 64, 64, 128]
+    t = [32, 32, 64, 64, 64, 64]
+    assert mc.load_tune_entry(path, "k") is None
+    assert mc.store_tune_entry(path, "k", b, t)
+    assert mc.load_tune_entry(path, "k") == (b, t)
+    assert mc.store_tune_entry(path, "other", t, b)
+    assert mc.load_tune_entry(path, "k") == (b, t)
+    import torch
+    old = mc.tune_get(torch.float64)
+    try:
+        mc.tune_set(b, t, torch.float64)
+        assert mc.tune_get(torch.float64) == (b, t)
+    finally:
+        mc.tune_set(*old, torch.float64)
+    with open(path, "w") as f:
+        f.write("{not json")
+    assert mc.load_tune_entry(path, "k") is None
+    with open(path, "w") as f:
+        f.write('{"k": {"b": [1, 2], "tile": [32]}}')
+    assert mc.load_tune_entry(path, "k") is None

@@ -188,3 +188,25 @@ def test_batched_plan_routes_large_members():
     plan.replay()
     torch.cuda.synchronize()
     assert plan.results() == routed
+
+
+def test_autotune_cached_stores_and_reuses(tmp_path):
+    """autotune_cached: the first call tunes and stores the table, the second
+    reads it back from the cache file; the table the library then holds is
+    valid and the batched results are unchanged by it."""
+    path = str(tmp_path / "tune.json")
+    old = mc.tune_get(torch.float64)
+    try:
+        b1, t1, src1 = mc.autotune_cached(torch.float64, "native", 256, DEV, path)
+        assert src1 == "tuned"
+        b2, t2, src2 = mc.autotune_cached(torch.float64, "native", 256, DEV, path)
+        assert (src2, b2, t2) == ("cache", b1, t1)
+        assert all(1 <= b <= 128 for b in b2) and all(t in (32, 64) for t in t2)
+        mats = [torch.from_numpy(synth.normal(n, 40 + n)).to(DEV) for n in (50, 120, 250)]
+        got = mc.logdet_batched(mats)
+        for m, g in zip(mats, got):
+            ref = O.slogdet(m.cpu().numpy())
+            assert g.sign == ref.sign
+            assert abs(g.logabsdet - ref.logabsdet) <= 1e-9 * max(1.0, abs(ref.logabsdet))
+    finally:
+        mc.tune_set(*old, torch.float64)
