@@ -482,6 +482,19 @@ int mc_lookahead_enable(int on);
 int mc_split_panel_enable(int on);
 
 /*
+ * Batched launches (mc_logdet_batched, mc_logdet_batched_factor) beside a
+ * blocked-path call.  On: the persistent kernel's workgroups that land on
+ * XCD 0 leave before taking a matrix, so the launch can run on one stream
+ * while blocked-path calls run on another (their column-split panels run on
+ * XCD 0 beside their trailing updates): the many small members of a batch
+ * on the other XCDs while its largest members go through the blocked path.
+ * Off (the default): the launch uses every XCD.  Results are the same
+ * either way.  Returns the previous setting (1 on, 0 off).  Process-wide
+ * and atomic; a call reads it once, when it enqueues.
+ */
+int mc_batched_spare_xcd0(int on);
+
+/*
  * Optional timing of the kernels that dominate a call, in two kinds:
  *
  * MC_PROF_UPDATE  the condensation update.  Plain path: the whole run of

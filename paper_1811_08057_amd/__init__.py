@@ -46,7 +46,7 @@ EXPORTS = ("mc_version", "mc_status_string", "mc_logdet_workspace",
            "mc_logdet_noalloc", "mc_logdet_batched_factor_workspace",
            "mc_logdet_batched_factor", "mc_logdet_batched_backward_workspace",
            "mc_logdet_batched_backward", "mc_gmm_loglik_workspace",
-           "mc_gmm_loglik")
+           "mc_gmm_loglik", "mc_batched_spare_xcd0")
 INFO_BADARG = -3
 TUNE_BUCKETS = (64, 128, 256, 512, 1024, None)  # upper size of each bucket
 
@@ -147,6 +147,8 @@ def lib() -> ctypes.CDLL:
     L.mc_gmm_loglik.argtypes = [vp, i64, i64, i64, vp, i64, i64, vp, vp, vp, vp,
                                 vp, ci, vp, vp, vp, sz, vp]
     L.mc_gmm_loglik.restype = ci
+    L.mc_batched_spare_xcd0.argtypes = [ci]
+    L.mc_batched_spare_xcd0.restype = ci
     _lib = L
     return L
 
@@ -337,12 +339,17 @@ class BatchedPlan:
     rest through one persistent mc_logdet_batched launch: the batched kernel
     condenses each matrix in one workgroup, which for the largest members
     takes longer than the whole-GPU blocked path does for all of them.
-    ``blocked_min_n=None`` keeps every member in the batched launch."""
+    When there are both, the batched launch runs on a second stream beside
+    the blocked calls, on the XCDs their column-split panels leave free
+    (mc_batched_spare_xcd0); ``concurrent=False`` runs them one after the
+    other.  ``blocked_min_n=None`` keeps every member in the batched
+    launch."""
 
     BLOCKED_MIN_N = 1024
 
     def __init__(self, mats, b: int = -1, update="native",
-                 blocked_min_n: Optional[int] = BLOCKED_MIN_N):
+                 blocked_min_n: Optional[int] = BLOCKED_MIN_N,
+                 concurrent: bool = True):
         if not mats:
             raise ValueError("empty batch")
         dev = mats[0].device
@@ -386,9 +393,30 @@ class BatchedPlan:
             self.work = torch.empty(nb, dtype=torch.uint8, device=dev)
             self.small_result = new_result(dev, len(sm))
         self.graph = None
+        self.concurrent = concurrent and bool(self.large) and bool(self.small)
+        # default priority, as every stream here
+        self.side = torch.cuda.Stream(dev) if self.concurrent else None
+
+    def _batched_call(self, sp: int) -> None:
+        st = lib().mc_logdet_batched(
+            self.ptrs.data_ptr(), self.ns.data_ptr(), self.ldas.data_ptr(),
+            len(self.small), self.n_max, _dtype_of(self.dtype), self.update,
+            self.b, self.small_result.data_ptr(), self.work.data_ptr(),
+            self.work.numel(), sp)
+        _check(st, "mc_logdet_batched")
 
     def run(self, stream: Optional[torch.cuda.Stream] = None) -> None:
-        sp = _stream_ptr(stream, self.device)
+        main = stream if stream is not None else torch.cuda.current_stream(self.device)
+        sp = main.cuda_stream
+        if self.concurrent:
+            # the small members on the side stream, off XCD 0, beside the
+            # large members' blocked calls on this one
+            self.side.wait_stream(main)
+            old = lib().mc_batched_spare_xcd0(1)
+            try:
+                self._batched_call(self.side.cuda_stream)
+            finally:
+                lib().mc_batched_spare_xcd0(old)
         for i in self.large:
             m = self.mats[i]
             st = lib().mc_logdet(m.data_ptr(), m.shape[0], _square_rows(m),
@@ -397,13 +425,10 @@ class BatchedPlan:
                                  self.blocked_work.data_ptr(),
                                  self.blocked_work.numel(), sp)
             _check(st, "mc_logdet")
-        if self.small:
-            st = lib().mc_logdet_batched(
-                self.ptrs.data_ptr(), self.ns.data_ptr(), self.ldas.data_ptr(),
-                len(self.small), self.n_max, _dtype_of(self.dtype), self.update,
-                self.b, self.small_result.data_ptr(), self.work.data_ptr(),
-                self.work.numel(), sp)
-            _check(st, "mc_logdet_batched")
+        if self.concurrent:
+            main.wait_stream(self.side)
+        elif self.small:
+            self._batched_call(sp)
 
     def capture(self) -> None:
         self.run()  # warm-up outside the capture (kernel attributes)
@@ -752,10 +777,29 @@ class MCLogDetBatched(torch.autograd.Function):
         lus = [None] * len(mats)
         perms = [None] * len(mats)
         res = [None] * len(mats)
+        main = torch.cuda.current_stream(dev)
+        side = None
+        if small and big:
+            # the small members' batched factor launch on a second stream,
+            # off XCD 0, beside the large members' blocked factor calls
+            side = torch.cuda.Stream(dev)
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
+                old = lib().mc_batched_spare_xcd0(1)
+                try:
+                    sl, sp, sr = factor_batched([mats[k] for k in small], b=b,
+                                                update=update)
+                finally:
+                    lib().mc_batched_spare_xcd0(old)
+        elif small:
+            sl, sp, sr = factor_batched([mats[k] for k in small], b=b, update=update)
         for k in big:
             lus[k], perms[k], res[k] = factor(mats[k], b=b, update=update)
+        if side is not None:
+            main.wait_stream(side)
+            for t in [*sl, *sp, sr]:
+                t.record_stream(main)  # made on the side stream, used here
         if small:
-            sl, sp, sr = factor_batched([mats[k] for k in small], b=b, update=update)
             for i, k in enumerate(small):
                 lus[k], perms[k], res[k] = sl[i], sp[i], sr[i:i + 1]
         fwd = torch.cat(res).to(dev)

@@ -265,6 +265,8 @@ extern "C" int mc_lookahead_enable(int on)
 
 extern "C" int mc_split_panel_enable(int on) { return split_panel_set(on); }
 
+extern "C" int mc_batched_spare_xcd0(int on) { return batched_spare_xcc0(on); }
+
 extern "C" mc_status mc_profile_enable(int on)
 {
     g_prof.on = on != 0;
@@ -426,6 +428,7 @@ static mc_status batched_call(const void* const* A_array, const int64_t* n_array
     a.region_stride = batched_region_bytes(n_max, dtype, t, with_w);
     a.out = out;
     a.perm_array = perm_array;
+    a.skip_xcc0 = batched_spare_xcc0_on() ? 1 : 0;
     const hipError_t e = launch_batched(a, dtype, batched_lds_bytes(dtype, t), st);
     return note_hip_error(e) == hipSuccess ? MC_OK : MC_ERR_HIP;
 }

@@ -39,7 +39,14 @@ struct BatchArgs {
     // the factor call: device array of each matrix's perm output (the
     // matrices in A_array are then factored in place); null otherwise
     int32_t* const* perm_array = nullptr;
+    // workgroups that land on XCD 0 leave at once (a blocked-path call may
+    // run beside the launch, its column-split panels on XCD 0)
+    int skip_xcc0 = 0;
 };
+
+// Process-wide: batched launches leave XCD 0 alone (read once per call).
+int batched_spare_xcc0(int on);
+bool batched_spare_xcc0_on();
 
 size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t,
                             bool with_w = true);

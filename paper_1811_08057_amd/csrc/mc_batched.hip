@@ -13,6 +13,7 @@
 // Panel width b and the trailing-update tile come from a small table keyed
 // by size bucket (filled by mc_autotune_batched, or defaults).
 #include <algorithm>
+#include <atomic>
 
 #include "mc_batched.h"
 #include "mc_device.h"
@@ -639,6 +640,7 @@ batched_persistent(BatchArgs a)
     extern __shared__ unsigned char smem_raw[];
     __shared__ WgShared sh;
     T* lds = reinterpret_cast<T*>(smem_raw);
+    if (a.skip_xcc0 && xcc_id() == 0) return; // before taking any matrix
     for (;;) {
         if (threadIdx.x == 0) sh.qidx = atomicAdd(a.counter, 1);
         __syncthreads();
@@ -675,6 +677,11 @@ batched_persistent(BatchArgs a)
 }
 
 // ------------------------------------------------------------------ host
+
+static std::atomic<bool> g_spare_xcc0{false};
+
+int batched_spare_xcc0(int on) { return g_spare_xcc0.exchange(on != 0) ? 1 : 0; }
+bool batched_spare_xcc0_on() { return g_spare_xcc0.load(); }
 
 size_t batched_region_bytes(int64_t n_max, int dtype, const TuneTable& t,
                             bool with_w)
