@@ -69,6 +69,33 @@ __device__ __forceinline__ void counter_tiles(const GemmArgs<T>& g, int bm, int 
 // 27.4 against 22.9 on the seven XCDs beside a panel chain.  In FP32 the
 // same 16 wavefronts fit twice per compute unit without C (49 VGPRs), which
 // is faster still: 65.7 against 56.0 TFLOP/s with C and 51.2 for 8.
+// Operand loads through buffer descriptors: a lane whose element lies
+// outside the operand takes an offset past the descriptor's range and reads
+// 0 (the hardware's range check), so a load needs no branch, and nothing
+// consumes its value before the LDS store that follows the K chunk's
+// products (a load inside a branch, with its value used there, made the
+// compiler wait for it at once).
+constexpr uint32_t kOutOfRange = 0x7ffffff0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const void* base, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                             (int)std::min<int64_t>(bytes, 0x7fffffff), 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T operand_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off);
+template <>
+__device__ __forceinline__ double operand_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float operand_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
 template <class P, int WGM, int WGN, int TM, int TN, bool PF, int KC = 16>
 __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
                                             int64_t rb, int64_t cb, int tid)
@@ -86,24 +113,28 @@ __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
     const int col_in = lane & 15, kq_lane = lane >> 4;
 
     T pa[PA], pb[PB];
+    // L's rows rb.. (rows past M lie past the range) and U's K rows from
+    // column c0 + cb
+    const __amdgpu_buffer_rsrc_t rl = operand_rsrc(
+        g.L + rb * g.ldl, sizeof(T) * std::min<int64_t>(BM, g.M - rb) * g.ldl);
+    const __amdgpu_buffer_rsrc_t ru = operand_rsrc(
+        g.U + g.c0 + cb, sizeof(T) * ((int64_t)(g.K - 1) * g.ldu + (g.N - cb)));
     auto gload = [&](int k0) {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
             const int e = tid + p * NT;
             const int rr = e / KC, kk = e - rr * KC;
-            const int64_t row = rb + rr;
-            pa[p] = (e < BM * KC && row < g.M && k0 + kk < g.K)
-                        ? -g.L[row * g.ldl + k0 + kk]
-                        : T(0);
+            const bool ok = e < BM * KC && k0 + kk < g.K;
+            pa[p] = operand_load<T>(
+                rl, ok ? (uint32_t)(sizeof(T) * (rr * g.ldl + k0 + kk)) : kOutOfRange);
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
             const int e = tid + p * NT;
             const int kb = e / BN, cc = e - kb * BN;
-            const int64_t col = cb + cc;
-            pb[p] = (e < BN * KC && col < g.N && k0 + kb < g.K)
-                        ? g.U[(int64_t)(k0 + kb) * g.ldu + g.c0 + col]
-                        : T(0);
+            const bool ok = e < BN * KC && cb + cc < g.N && k0 + kb < g.K;
+            pb[p] = operand_load<T>(
+                ru, ok ? (uint32_t)(sizeof(T) * ((int64_t)(k0 + kb) * g.ldu + cc)) : kOutOfRange);
         }
     };
     auto sstore = [&](int buf) {
@@ -111,7 +142,7 @@ __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
         for (int p = 0; p < PA; ++p) {
             const int e = tid + p * NT;
             const int rr = e / KC, kk = e - rr * KC;
-            if (e < BM * KC) As[buf][kk][rr] = pa[p];
+            if (e < BM * KC) As[buf][kk][rr] = -pa[p];
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
@@ -121,6 +152,19 @@ __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
         }
     };
 
+    // PF: the sources of this wavefront's columns, read first so that no
+    // later wait is for them alone
+    int csrc[TN];
+    if (PF) {
+        const __amdgpu_buffer_rsrc_t rc =
+            operand_rsrc(g.colsrc + g.c0 + cb, sizeof(int) * (g.N - cb));
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj) {
+            const int cc = wn * 16 * TN + tj * 16 + col_in;
+            csrc[tj] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rc, cb + cc < g.N ? (uint32_t)(sizeof(int) * cc) : kOutOfRange, 0, 0);
+        }
+    }
     gload(0);
 
     // the product -L U accumulates from zero; C joins it in the epilogue, so
@@ -144,18 +188,19 @@ __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
             // the old C, read behind the next chunk's operands: loads
             // complete in order, so no wait before the chunk after that
             // includes these, and by then they are in
+            const __amdgpu_buffer_rsrc_t rcm = operand_rsrc(
+                g.C + (g.r0 + rb) * g.ldc, sizeof(T) * std::min<int64_t>(BM, g.M - rb) * g.ldc);
 #pragma unroll
             for (int tj = 0; tj < TN; ++tj) {
-                const int64_t col = cb + wn * 16 * TN + tj * 16 + col_in;
-                const int64_t src = col < g.N ? g.colsrc[g.c0 + col] : 0;
+                const bool okc = cb + wn * 16 * TN + tj * 16 + col_in < g.N;
 #pragma unroll
                 for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int64_t row = rb + wm * 16 * TM + ti * 16 + P::drow(lane, r);
-                        cpre[ti][tj][r] = (row < g.M && col < g.N)
-                                              ? g.C[(g.r0 + row) * g.ldc + src]
-                                              : T(0);
+                        const int rr = wm * 16 * TM + ti * 16 + P::drow(lane, r);
+                        cpre[ti][tj][r] = operand_load<T>(
+                            rcm, okc ? (uint32_t)(sizeof(T) * (rr * g.ldc + csrc[tj]))
+                                     : kOutOfRange);
                     }
             }
         }
