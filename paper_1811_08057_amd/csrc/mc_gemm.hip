@@ -289,18 +289,72 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
 // 16 WT WG).
 template <int WT, int WG>
 __device__ __forceinline__ void bf16x3_tile(const GemmArgs<float>& g, int64_t rb,
-                                            int64_t cb)
+                                            int64_t cb, int tid)
 {
     constexpr int BT = 16 * WT * WG, NT = 64 * WG * WG;
     constexpr int KC = 32;
     constexpr int LD = KC + 8; // bf16 elements per LDS row (16-byte aligned)
-    __shared__ __attribute__((aligned(16))) __bf16 Ah[BT][LD], Al[BT][LD];
-    __shared__ __attribute__((aligned(16))) __bf16 Bh[BT][LD], Bl[BT][LD];
+    constexpr int PA = (BT * KC + NT - 1) / NT;
+    // two buffers: chunk c+1 is read into registers while chunk c feeds the
+    // matrix cores, then split and parked in the other buffer
+    __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BT][LD], Al[2][BT][LD];
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BT][LD], Bl[2][BT][LD];
 
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wid / WG, wn = wid % WG;
     const int col_in = lane & 15, kg = lane >> 4;
+
+    const __amdgpu_buffer_rsrc_t rl = operand_rsrc(
+        g.L + rb * g.ldl, sizeof(float) * std::min<int64_t>(BT, g.M - rb) * g.ldl);
+    const __amdgpu_buffer_rsrc_t ru = operand_rsrc(
+        g.U + g.c0 + cb, sizeof(float) * ((int64_t)(g.K - 1) * g.ldu + (g.N - cb)));
+    float pa[PA], pb[PA];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const int e = tid + p * NT;
+            { // A = -L: row-major in global and in LDS (k contiguous)
+                const int rr = e / KC, kk = e - rr * KC;
+                const bool ok = e < BT * KC && k0 + kk < g.K;
+                pa[p] = operand_load<float>(
+                    rl, ok ? (uint32_t)(sizeof(float) * (rr * g.ldl + k0 + kk)) : kOutOfRange);
+            }
+            { // B = U: k-major in global, stored column-major (k contiguous)
+                const int kk = e / BT, cc = e - kk * BT;
+                const bool ok = e < BT * KC && cb + cc < g.N && k0 + kk < g.K;
+                pb[p] = operand_load<float>(
+                    ru, ok ? (uint32_t)(sizeof(float) * ((int64_t)(k0 + kk) * g.ldu + cc))
+                           : kOutOfRange);
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const int e = tid + p * NT;
+            if (e < BT * KC) {
+                const int rr = e / KC, kk = e - rr * KC;
+                split_bf16(-pa[p], Ah[buf][rr][kk], Al[buf][rr][kk]);
+                const int kb = e / BT, cc = e - kb * BT;
+                split_bf16(pb[p], Bh[buf][cc][kb], Bl[buf][cc][kb]);
+            }
+        }
+    };
+
+    // the sources of this wavefront's columns, then the first chunk
+    int csrc[WT];
+    {
+        const __amdgpu_buffer_rsrc_t rc =
+            operand_rsrc(g.colsrc + g.c0 + cb, sizeof(int) * (g.N - cb));
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj) {
+            const int cc = wn * 16 * WT + tj * 16 + col_in;
+            csrc[tj] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rc, cb + cc < g.N ? (uint32_t)(sizeof(int) * cc) : kOutOfRange, 0, 0);
+        }
+    }
+    gload(0);
 
     f4 acc[WT][WT];
 #pragma unroll
@@ -308,35 +362,40 @@ __device__ __forceinline__ void bf16x3_tile(const GemmArgs<float>& g, int64_t rb
 #pragma unroll
         for (int tj = 0; tj < WT; ++tj) acc[ti][tj] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int k0 = 0; k0 < g.K; k0 += KC) {
-        // A = -L: row-major in global and in LDS (k contiguous)
-        for (int e = tid; e < BT * KC; e += NT) {
-            const int rr = e / KC, kk = e - rr * KC;
-            const int64_t row = rb + rr;
-            const float v = (row < g.M && k0 + kk < g.K)
-                                ? -g.L[row * g.ldl + k0 + kk]
-                                : 0.0f;
-            split_bf16(v, Ah[rr][kk], Al[rr][kk]);
+    sstore(0);
+    __syncthreads();
+    const int nch = (g.K + KC - 1) / KC;
+    float cpre[WT][WT][4]; // the tile's old C, read behind chunk 1's operands
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) gload((c + 1) * KC);
+        if (c == 0) {
+            const __amdgpu_buffer_rsrc_t rcm = operand_rsrc(
+                g.C + (g.r0 + rb) * g.ldc,
+                sizeof(float) * std::min<int64_t>(BT, g.M - rb) * g.ldc);
+#pragma unroll
+            for (int tj = 0; tj < WT; ++tj) {
+                const bool okc = cb + wn * 16 * WT + tj * 16 + col_in < g.N;
+#pragma unroll
+                for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rr = wm * 16 * WT + ti * 16 + 4 * kg + r;
+                        cpre[ti][tj][r] = operand_load<float>(
+                            rcm, okc ? (uint32_t)(sizeof(float) * (rr * g.ldc + csrc[tj]))
+                                     : kOutOfRange);
+                    }
+            }
         }
-        // B = U: k-major in global, stored column-major (k contiguous)
-        for (int e = tid; e < BT * KC; e += NT) {
-            const int kk = e / BT, cc = e - kk * BT;
-            const int64_t col = cb + cc;
-            const float v = (col < g.N && k0 + kk < g.K)
-                                ? g.U[(int64_t)(k0 + kk) * g.ldu + g.c0 + col]
-                                : 0.0f;
-            split_bf16(v, Bh[cc][kk], Bl[cc][kk]);
-        }
-        __syncthreads();
         bf8 ah[WT], al[WT], bh[WT], bl[WT];
 #pragma unroll
         for (int t = 0; t < WT; ++t) {
             const int ar = wm * 16 * WT + t * 16 + col_in;
             const int bc = wn * 16 * WT + t * 16 + col_in;
-            ah[t] = *reinterpret_cast<const bf8*>(&Ah[ar][8 * kg]);
-            al[t] = *reinterpret_cast<const bf8*>(&Al[ar][8 * kg]);
-            bh[t] = *reinterpret_cast<const bf8*>(&Bh[bc][8 * kg]);
-            bl[t] = *reinterpret_cast<const bf8*>(&Bl[bc][8 * kg]);
+            ah[t] = *reinterpret_cast<const bf8*>(&Ah[buf][ar][8 * kg]);
+            al[t] = *reinterpret_cast<const bf8*>(&Al[buf][ar][8 * kg]);
+            bh[t] = *reinterpret_cast<const bf8*>(&Bh[buf][bc][8 * kg]);
+            bl[t] = *reinterpret_cast<const bf8*>(&Bl[buf][bc][8 * kg]);
         }
 #pragma unroll
         for (int ti = 0; ti < WT; ++ti)
@@ -349,23 +408,23 @@ __device__ __forceinline__ void bf16x3_tile(const GemmArgs<float>& g, int64_t rb
                 acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     ah[ti], bh[tj], acc[ti][tj], 0, 0, 0);
             }
+        if (c + 1 < nch) sstore(buf ^ 1);
         __syncthreads();
     }
 
+    // C[dst] = C[src] + acc.  A moved column's source lies in the panel's
+    // column range, which no block writes.
 #pragma unroll
     for (int tj = 0; tj < WT; ++tj) {
         const int64_t col = cb + wn * 16 * WT + tj * 16 + col_in;
         if (col >= g.N) continue;
-        const int64_t src = g.colsrc[g.c0 + col];
 #pragma unroll
         for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = rb + wm * 16 * WT + ti * 16 + 4 * kg + r;
-                if (row < g.M) {
-                    float* crow = g.C + (g.r0 + row) * g.ldc;
-                    crow[g.c0 + col] = crow[src] + acc[ti][tj][r];
-                }
+                if (row < g.M)
+                    g.C[(g.r0 + row) * g.ldc + g.c0 + col] = cpre[ti][tj][r] + acc[ti][tj][r];
             }
     }
 }
@@ -376,7 +435,8 @@ gemm_bf16x3(GemmArgs<float> g)
 {
     if (g.state->status != kStatusOk) return;
     constexpr int BT = 16 * WT * WG;
-    bf16x3_tile<WT, WG>(g, (int64_t)blockIdx.y * BT, (int64_t)blockIdx.x * BT);
+    bf16x3_tile<WT, WG>(g, (int64_t)blockIdx.y * BT, (int64_t)blockIdx.x * BT,
+                        (int)threadIdx.x);
 }
 
 template <int WT, int WG>
@@ -387,7 +447,9 @@ gemm_bf16x3_spare(GemmArgs<float> g)
     if (g.state->status != kStatusOk) return;
     constexpr int BT = 16 * WT * WG;
     counter_tiles(g, BT, BT, [&](int64_t rb, int64_t cb) {
-        bf16x3_tile<WT, WG>(g, rb, cb);
+        int tid = (int)threadIdx.x; // formed afresh per tile (as gemm_scalar_spare)
+        asm volatile("" : "+v"(tid));
+        bf16x3_tile<WT, WG>(g, rb, cb, tid);
     });
 }
 
