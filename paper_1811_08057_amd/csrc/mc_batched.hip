@@ -322,7 +322,11 @@ __device__ void wg_trsm(Region<T>& r, int64_t n, int64_t s0, int nb, T* Xall)
 }
 
 // Trailing update C[pend:, pend:] <- C[., colsrc] - L U12 with tiles of
-// (32 WT) x (32 WT): 4 wavefronts in 2 x 2, WT x WT MFMA tiles each.
+// (32 WT) x (32 WT): 4 wavefronts in 2 x 2, WT x WT MFMA tiles each.  The
+// K loop is double-buffered: chunk c+1 is read into registers (buffer
+// loads, out-of-range entries reading 0, all in flight at once) while chunk
+// c feeds the matrix cores, then parked in the other LDS buffer; the tile's
+// old C is read behind chunk 1's operands, so the epilogue waits on no load.
 template <typename T, int WT>
 __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
                                T* lds)
@@ -331,16 +335,63 @@ __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
     constexpr int BT = 32 * WT;
     constexpr int KC = 16;
     constexpr int LD = BT + 16;
-    T* As = lds;            // [KC][LD]
-    T* Bs = lds + KC * LD;  // [KC][LD]
+    constexpr int PA = (BT * KC + kBT - 1) / kBT; // elements per thread per operand
+    T* As = lds;                // [2][KC][LD]
+    T* Bs = lds + 2 * KC * LD;  // [2][KC][LD]
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid >> 1, wn = wid & 1;
     const int cin = lane & 15, kl = lane >> 4;
     const int64_t pend = s0 + nb, M = n - pend;
     const int64_t tiles = (M + BT - 1) / BT;
-    const T* U = r.W + s0 * r.ldw;
+    const int nch = (nb + KC - 1) / KC;
+    const __amdgpu_buffer_rsrc_t rcs = operand_rsrc(r.colsrc + pend, sizeof(int) * M);
     for (int64_t t = 0; t < tiles * tiles; ++t) {
         const int64_t rb = (t / tiles) * BT, cb = (t % tiles) * BT;
+        // the tile's rows of L (M x nb, row stride nb) and of C, and U12's
+        // nb rows from the tile's first column (offsets stay below 2^31
+        // bytes for any matrix that fits in memory)
+        const int64_t rows = (M - rb) < BT ? (M - rb) : BT;
+        const __amdgpu_buffer_rsrc_t rl = operand_rsrc(r.L + rb * nb, sizeof(T) * rows * nb);
+        const __amdgpu_buffer_rsrc_t ru = operand_rsrc(
+            r.W + s0 * r.ldw + pend + cb, sizeof(T) * ((int64_t)(nb - 1) * r.ldw + (M - cb)));
+        const __amdgpu_buffer_rsrc_t rcm =
+            operand_rsrc(r.W + (pend + rb) * r.ldw, sizeof(T) * rows * r.ldw);
+        T pa[PA], pb[PA];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int p = 0; p < PA; ++p) {
+                const int e = tid + p * kBT;
+                const int rr = e / KC, kk = e - rr * KC;
+                const bool oka = e < BT * KC && k0 + kk < nb; // rows past M: past the range
+                pa[p] = operand_load<T>(
+                    rl, oka ? (uint32_t)(sizeof(T) * (rr * nb + k0 + kk)) : kOutOfRange);
+                const int kb = e / BT, cc = e - kb * BT;
+                const bool okb = e < BT * KC && cb + cc < M && k0 + kb < nb;
+                pb[p] = operand_load<T>(
+                    ru, okb ? (uint32_t)(sizeof(T) * ((int64_t)(k0 + kb) * r.ldw + cc))
+                            : kOutOfRange);
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int p = 0; p < PA; ++p) {
+                const int e = tid + p * kBT;
+                if (e < BT * KC) {
+                    const int rr = e / KC, kk = e - rr * KC;
+                    As[(buf * KC + kk) * LD + rr] = -pa[p];
+                    const int kb = e / BT, cc = e - kb * BT;
+                    Bs[(buf * KC + kb) * LD + cc] = pb[p];
+                }
+            }
+        };
+        int csrc[WT];
+#pragma unroll
+        for (int tj = 0; tj < WT; ++tj) {
+            const int64_t col = cb + wn * 16 * WT + tj * 16 + cin;
+            csrc[tj] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rcs, col < M ? (uint32_t)(sizeof(int) * col) : kOutOfRange, 0, 0);
+        }
+        gload(0);
         typename P::Acc acc[WT][WT];
 #pragma unroll
         for (int a = 0; a < WT; ++a)
@@ -348,27 +399,34 @@ __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
             for (int b = 0; b < WT; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[a][b][q] = T(0);
-        for (int k0 = 0; k0 < nb; k0 += KC) {
-            for (int e = tid; e < BT * KC; e += kBT) {
-                const int rr = e / KC, kk = e - rr * KC;
-                const int64_t row = rb + rr;
-                As[kk * LD + rr] = (row < M && k0 + kk < nb)
-                                       ? -r.L[row * nb + k0 + kk]
-                                       : T(0);
-                const int kb = e / BT, cc = e - kb * BT;
-                const int64_t col = cb + cc;
-                Bs[kb * LD + cc] = (col < M && k0 + kb < nb)
-                                       ? U[(int64_t)(k0 + kb) * r.ldw + pend + col]
-                                       : T(0);
+        sstore(0);
+        __syncthreads();
+        T cpre[WT][WT][4];
+        for (int c = 0; c < nch; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < nch) gload((c + 1) * KC);
+            if (c == 0) {
+#pragma unroll
+                for (int tj = 0; tj < WT; ++tj) {
+                    const bool okc = cb + wn * 16 * WT + tj * 16 + cin < M;
+#pragma unroll
+                    for (int ti = 0; ti < WT; ++ti)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int rr = wm * 16 * WT + ti * 16 + P::drow(lane, q);
+                            cpre[ti][tj][q] = operand_load<T>(
+                                rcm, okc ? (uint32_t)(sizeof(T) * (rr * r.ldw + csrc[tj]))
+                                         : kOutOfRange);
+                        }
+                }
             }
-            __syncthreads();
 #pragma unroll
             for (int kq = 0; kq < KC; kq += 4) {
                 T a[WT], b[WT];
 #pragma unroll
                 for (int q = 0; q < WT; ++q) {
-                    a[q] = As[(kq + kl) * LD + wm * 16 * WT + q * 16 + cin];
-                    b[q] = Bs[(kq + kl) * LD + wn * 16 * WT + q * 16 + cin];
+                    a[q] = As[(buf * KC + kq + kl) * LD + wm * 16 * WT + q * 16 + cin];
+                    b[q] = Bs[(buf * KC + kq + kl) * LD + wn * 16 * WT + q * 16 + cin];
                 }
 #pragma unroll
                 for (int ti = 0; ti < WT; ++ti)
@@ -376,22 +434,22 @@ __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
                     for (int tj = 0; tj < WT; ++tj)
                         acc[ti][tj] = P::mma(a[ti], b[tj], acc[ti][tj]);
             }
+            if (c + 1 < nch) sstore(buf ^ 1);
             __syncthreads();
         }
+        // C[dst] = C[src] + acc (a moved column's source lies in the
+        // panel's column range, which no tile writes)
 #pragma unroll
         for (int tj = 0; tj < WT; ++tj) {
             const int64_t col = cb + wn * 16 * WT + tj * 16 + cin;
             if (col >= M) continue;
-            const int64_t src = r.colsrc[pend + col];
 #pragma unroll
             for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t row = rb + wm * 16 * WT + ti * 16 + P::drow(lane, q);
-                    if (row < M) {
-                        T* crow = r.W + (pend + row) * r.ldw;
-                        crow[pend + col] = crow[src] + acc[ti][tj][q];
-                    }
+                    if (row < M)
+                        r.W[(pend + row) * r.ldw + pend + col] = cpre[ti][tj][q] + acc[ti][tj][q];
                 }
         }
     }
@@ -699,7 +757,7 @@ size_t batched_lds_bytes(int dtype, const TuneTable& t)
     int64_t bmax = 16;
     for (int k = 0; k < kTuneBuckets; ++k) bmax = std::max<int64_t>(bmax, t.b[k]);
     const size_t trsm = (size_t)elem * 64 * (size_t)(((bmax + 15) / 16) * 16 + 1);
-    const size_t gemm = (size_t)elem * 2 * 16 * (64 + 16);
+    const size_t gemm = (size_t)elem * 2 * 2 * 16 * (64 + 16); // A and B, two buffers
     const size_t bf16 = 4 * 64 * (32 + 8) * 2;
     return std::max(trsm, std::max(gemm, bf16));
 }

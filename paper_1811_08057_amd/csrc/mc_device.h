@@ -147,4 +147,32 @@ __device__ __forceinline__ int xcc_id()
     return x & 0xf;
 }
 
+// Operand loads through buffer descriptors: a lane whose element lies
+// outside the operand takes an offset past the descriptor's range and reads
+// 0 (the hardware's range check), so a load needs no branch, and nothing
+// consumes its value before the LDS store that follows the K chunk's
+// products (a load inside a branch, with its value used there, made the
+// compiler wait for it at once).
+constexpr uint32_t kOutOfRange = 0x7ffffff0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const void* base, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                             (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff),
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T operand_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off);
+template <>
+__device__ __forceinline__ double operand_load<double>(__amdgpu_buffer_rsrc_t r,
+                                                       uint32_t byte_off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float operand_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
 } // namespace mc

@@ -69,33 +69,6 @@ __device__ __forceinline__ void counter_tiles(const GemmArgs<T>& g, int bm, int 
 // 27.4 against 22.9 on the seven XCDs beside a panel chain.  In FP32 the
 // same 16 wavefronts fit twice per compute unit without C (49 VGPRs), which
 // is faster still: 65.7 against 56.0 TFLOP/s with C and 51.2 for 8.
-// Operand loads through buffer descriptors: a lane whose element lies
-// outside the operand takes an offset past the descriptor's range and reads
-// 0 (the hardware's range check), so a load needs no branch, and nothing
-// consumes its value before the LDS store that follows the K chunk's
-// products (a load inside a branch, with its value used there, made the
-// compiler wait for it at once).
-constexpr uint32_t kOutOfRange = 0x7ffffff0u;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const void* base, int64_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
-                                             (int)std::min<int64_t>(bytes, 0x7fffffff), 0x00020000);
-}
-
-template <typename T>
-__device__ __forceinline__ T operand_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off);
-template <>
-__device__ __forceinline__ double operand_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
-}
-template <>
-__device__ __forceinline__ float operand_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
-}
-
 template <class P, int WGM, int WGN, int TM, int TN, bool PF, int KC = 16>
 __device__ __forceinline__ void scalar_tile(const GemmArgs<typename P::T>& g,
                                             int64_t rb, int64_t cb, int tid)
