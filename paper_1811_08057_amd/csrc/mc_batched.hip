@@ -175,16 +175,105 @@ __device__ int wg_pivot_row(Region<T>& r, int64_t n, int64_t s, WgShared& sh)
     return st;
 }
 
+// Rows through buffer descriptors: a position past the row (or any
+// position of a zero-length row) reads 0 and a store there is dropped, so a
+// thread's loads go out together, with no branch between them.
+constexpr uint32_t kPastRow = 0x7ffffff0u;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T* row, int64_t len)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(row), 0, (int)(sizeof(T) * len),
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T row_load(__amdgpu_buffer_rsrc_t r, int64_t j, int64_t len)
+{
+    return operand_load<T>(r, j < len ? (uint32_t)(sizeof(T) * j) : kPastRow);
+}
+
+__device__ __forceinline__ void row_store(double v, __amdgpu_buffer_rsrc_t r, int64_t j,
+                                          int64_t len)
+{
+    typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, v), r,
+                                          j < len ? (uint32_t)(8 * j) : kPastRow, 0, 0);
+}
+
+__device__ __forceinline__ void row_store(float v, __amdgpu_buffer_rsrc_t r, int64_t j,
+                                          int64_t len)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r,
+                                          j < len ? (uint32_t)(4 * j) : kPastRow, 0, 0);
+}
+
+// The later panel rows' update of step s (rows s+1.., R of them): a
+// thread takes columns s+1+tid+q kBT (q < QC) of every row, rows in groups
+// of RG whose loads go out together, the next group's loads in flight while
+// this group's results are stored.  QC x RG = 16 loads a group: fewer
+// columns a thread (shorter rows) take more rows a group.  sc, sx: each
+// row's entry at l and its old entry at s (already staged).
+template <typename T, int QC, int RG>
+__device__ void panel_rows_update(T* W, int64_t ldw, int64_t n, int64_t s, int64_t l, int R,
+                                  const T* sc, const T* sx)
+{
+    const int tid = threadIdx.x;
+    const __amdgpu_buffer_rsrc_t rrs = row_rsrc(W + s * ldw, n);
+    for (int64_t jb = s + 1 + tid; jb < n; jb += QC * kBT) {
+        T rv[QC];
+#pragma unroll
+        for (int q = 0; q < QC; ++q) rv[q] = row_load<T>(rrs, jb + q * kBT, n);
+        auto rrow = [&](int i) { // row s+1+i, or nothing past the panel
+            return row_rsrc(W + (s + 1 + (i < R ? i : 0)) * ldw, i < R ? n : 0);
+        };
+        auto load_group = [&](int i0, T (&xv)[RG][QC]) {
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+                const __amdgpu_buffer_rsrc_t rr = rrow(i0 + g);
+#pragma unroll
+                for (int q = 0; q < QC; ++q) xv[g][q] = row_load<T>(rr, jb + q * kBT, n);
+            }
+        };
+        auto store_group = [&](int i0, const T (&xv)[RG][QC]) {
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+                const int i = i0 + g;
+                const __amdgpu_buffer_rsrc_t rr = rrow(i);
+                const T c = sc[i < R ? i : 0], xs = sx[i < R ? i : 0];
+#pragma unroll
+                for (int q = 0; q < QC; ++q) {
+                    const int64_t j = jb + q * kBT;
+                    row_store(fma(-c, rv[q], (j == l) ? xs : xv[g][q]), rr, j, n);
+                }
+            }
+        };
+        T xa[RG][QC], xb[RG][QC];
+        load_group(0, xa);
+        for (int i0 = 0; i0 < R; i0 += 2 * RG) {
+            if (i0 + RG < R) load_group(i0 + RG, xb);
+            store_group(i0, xa);
+            if (i0 + 2 * RG < R) load_group(i0 + 2 * RG, xa);
+            if (i0 + RG < R) store_group(i0 + RG, xb);
+        }
+    }
+}
+
 // Step s inside the panel [s0, pend): exchange positions s, l in the
 // earlier rows (the panel's own, or every row above when the factors are
-// kept: rows above hold U entries there); update the later panel rows (one
-// wavefront per row).
+// kept: rows above hold U entries there); update the later panel rows:
+// row i's position s takes c_i (its entry at l: the pivot column moves to
+// s), position l the old entry at s, and every position j > s loses c_i
+// times the factored pivot row's entry.  Short rows (at most kBT
+// positions right of s): one wavefront a row, the lanes along it (two
+// round trips a row at most); longer rows: the grouped form above, after
+// each row's entries at l and s are staged in `lds` (2 kMaxPanel elements).
 template <typename T>
 __device__ void wg_panel_update(Region<T>& r, int64_t n, int64_t s,
                                 int64_t s0, int64_t pend, int64_t l,
-                                bool factor)
+                                bool factor, T* lds)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x;
     T* W = r.W;
     const int64_t ldw = r.ldw;
     if (l != s)
@@ -194,21 +283,42 @@ __device__ void wg_panel_update(Region<T>& r, int64_t n, int64_t s,
             ru[s] = ru[l];
             ru[l] = a;
         }
-    const T* rs = W + s * ldw;
-    for (int64_t i = s + 1 + wid; i < pend; i += kBT / kWave) {
-        T* ri = W + i * ldw;
-        const T c = ri[l]; // every lane reads it before any lane writes
-        for (int64_t j = s + 1 + lane; j < n; j += kWave) {
-            T x;
-            if (j == l) {
-                x = ri[s];
-                ri[s] = c;
-            } else {
-                x = ri[j];
+    const int64_t cols = n - s - 1;
+    if (cols <= kBT) {
+        const int lane = tid & 63, wid = tid >> 6;
+        const T* rs = W + s * ldw;
+        for (int64_t i = s + 1 + wid; i < pend; i += kBT / kWave) {
+            T* ri = W + i * ldw;
+            const T c = ri[l]; // every lane reads it before any lane writes
+            for (int64_t j = s + 1 + lane; j < n; j += kWave) {
+                T x;
+                if (j == l) {
+                    x = ri[s];
+                    ri[s] = c;
+                } else {
+                    x = ri[j];
+                }
+                ri[j] = fma(-c, rs[j], x);
             }
-            ri[j] = fma(-c, rs[j], x);
         }
+        __syncthreads();
+        return;
     }
+    const int R = (int)(pend - s - 1); // later panel rows
+    T* sc = lds;
+    T* sx = lds + kMaxPanel;
+    if (tid < R) {
+        T* ri = W + (s + 1 + tid) * ldw;
+        const T c = ri[l];
+        sx[tid] = ri[s];
+        sc[tid] = c;
+        ri[s] = c;
+    }
+    __syncthreads();
+    if (cols <= 2 * kBT)
+        panel_rows_update<T, 2, 8>(W, ldw, n, s, l, R, sc, sx);
+    else
+        panel_rows_update<T, 4, 4>(W, ldw, n, s, l, R, sc, sx);
     __syncthreads();
 }
 
@@ -622,7 +732,7 @@ __device__ void wg_factor(const T* __restrict__ A, int64_t n, int64_t lda,
         }
         for (int64_t s = s0; s < pend; ++s) {
             const int64_t l = r.piv_pos[s];
-            wg_panel_update<T>(r, n, s, s0, pend, l, factor);
+            wg_panel_update<T>(r, n, s, s0, pend, l, factor, lds);
             if (s + 1 < pend) {
                 st = wg_pivot_row<T>(r, n, s + 1, sh);
                 if (st != kStatusOk) {
