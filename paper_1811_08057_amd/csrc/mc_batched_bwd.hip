@@ -159,7 +159,7 @@ bbwd_invert(BatchedBwdArgs a)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kQB)
+__global__ void __launch_bounds__(kQB, 2)
 bbwd_persistent(BatchedBwdArgs a)
 {
     extern __shared__ unsigned char smem_raw[];

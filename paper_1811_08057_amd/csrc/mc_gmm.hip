@@ -50,11 +50,26 @@ __device__ void gmm_item(const GmmArgs& a, int k, int P0, T* lds, T* slot)
     const int32_t* perm = a.perm_array[k];
     const int64_t ldy = a.ldy;
     // right-hand side j: the residual of point p0 + j, in position order of
-    // the unpermuted columns (the substitutions see positions 0..d-1)
-    for (int64_t e = tid; e < (int64_t)w * d; e += kQB) {
-        const int j = (int)(e / d);
-        const int64_t s = e - (int64_t)j * d;
-        slot[j * ldy + s] = X[(p0 + j) * a.ldx + s] - mu[s];
+    // the unpermuted columns (the substitutions see positions 0..d-1); each
+    // thread's eight loads of a round go out together
+    for (int64_t e0 = tid; e0 < (int64_t)w * d; e0 += 8 * kQB) {
+        T xv[8], mv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = e0 + u * kQB;
+            const int j = (int)(e / d);
+            const int64_t s = e - (int64_t)j * d;
+            const bool in = e < (int64_t)w * d;
+            xv[u] = in ? X[(p0 + j) * a.ldx + s] : T(0);
+            mv[u] = in ? mu[s] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = e0 + u * kQB;
+            const int j = (int)(e / d);
+            const int64_t s = e - (int64_t)j * d;
+            if (e < (int64_t)w * d) slot[j * ldy + s] = xv[u] - mv[u];
+        }
     }
     __syncthreads();
     T* Xl = lds;
@@ -63,14 +78,46 @@ __device__ void gmm_item(const GmmArgs& a, int k, int P0, T* lds, T* slot)
     const T* inv = reinterpret_cast<const T*>(static_cast<const unsigned char*>(a.inv) +
                                               (size_t)k * a.inv_stride);
     lu_solve_rhs<T>(LU, ld, d, inv, slot, ldy, w, 0, false, Xl, As, Bs, As);
-    // q_j = sum_s r_j[perm[s]] y_j[s]: each wavefront takes 16 points
-    for (int j = wv; j < w; j += kQB / kWave) {
+    // q_j = sum_s r_j[perm[s]] y_j[s]: wavefront wv takes points wv + 4 i,
+    // positions in rounds of 8 a lane whose loads go out together; with
+    // d <= 512 (one round) the column sources and the mean's entries there
+    // are read once for all the points
+    const __amdgpu_buffer_rsrc_t rperm = operand_rsrc(perm, sizeof(int32_t) * d);
+    auto round_sources = [&](int64_t s0, int (&cv)[8], T (&mv)[8]) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t sidx = s0 + lane + u * kWave;
+            cv[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rperm, sidx < d ? (uint32_t)(sizeof(int32_t) * sidx) : kOutOfRange, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mv[u] = mu[cv[u]]; // past d: column 0, weight 0 below
+    };
+    auto round_sum = [&](int64_t s0, int j, const int (&cv)[8], const T (&mv)[8]) {
         const T* rx = X + (p0 + j) * a.ldx;
-        const T* yj = slot + j * ldy;
+        const __amdgpu_buffer_rsrc_t ry = operand_rsrc(slot + j * ldy, sizeof(T) * d);
+        T xv[8], yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t sidx = s0 + lane + u * kWave;
+            xv[u] = rx[cv[u]];
+            yv[u] = operand_load<T>(ry, sidx < d ? (uint32_t)(sizeof(T) * sidx) : kOutOfRange);
+        }
         double acc = 0.0;
-        for (int64_t s = lane; s < d; s += kWave) {
-            const int c = perm[s];
-            acc += (double)(rx[c] - mu[c]) * (double)yj[s];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)(xv[u] - mv[u]) * (double)yv[u];
+        return acc;
+    };
+    int cv0[8];
+    T mv0[8];
+    round_sources(0, cv0, mv0);
+    for (int j = wv; j < w; j += kQB / kWave) {
+        double acc = round_sum(0, j, cv0, mv0);
+        for (int64_t s0 = 8 * kWave; s0 < d; s0 += 8 * kWave) {
+            int cv[8];
+            T mv[8];
+            round_sources(s0, cv, mv);
+            acc += round_sum(s0, j, cv, mv);
         }
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
@@ -80,7 +127,7 @@ __device__ void gmm_item(const GmmArgs& a, int k, int P0, T* lds, T* slot)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kQB)
+__global__ void __launch_bounds__(kQB, 2)
 gmm_items(GmmArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -95,7 +142,9 @@ gmm_items(GmmArgs a)
         const int64_t q = sh.q;
         __syncthreads();
         if (q >= total) break;
-        gmm_item<T>(a, (int)(q % a.k), (int)(q / a.k), lds, slot);
+        // component-major: the workgroups at work at any time share one
+        // or two components, whose factors then stay in the L2
+        gmm_item<T>(a, (int)(q / pb), (int)(q % pb), lds, slot);
     }
 }
 

@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mc_device.h"
 #include "mc_mfma.h"
 
 namespace mc {
@@ -42,6 +43,13 @@ __device__ inline void block_update(const T* __restrict__ Amat, int64_t lda, int
     const int ci = lane & 15, kq = lane >> 4;
     if (k_lo >= k_hi) return;
     T pa[PER], pb[PER];
+    // the block's 64 rows of A from column 0 and the w rows of Yt, through
+    // buffer descriptors (an element past a row's K range or past the rows
+    // reads 0: no branch, and the loads go out together)
+    const int64_t arows = (r_end - r0) < kQW ? (r_end - r0) : kQW;
+    const __amdgpu_buffer_rsrc_t ra =
+        operand_rsrc(Amat + r0 * lda, sizeof(T) * ((arows - 1) * lda + k_hi));
+    const __amdgpu_buffer_rsrc_t rb = operand_rsrc(Yt, sizeof(T) * ((int64_t)(w - 1) * ldy + k_hi));
     auto gload = [&](int64_t k0) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -49,9 +57,10 @@ __device__ inline void block_update(const T* __restrict__ Amat, int64_t lda, int
             const int r = e / kQKC, kk = e - r * kQKC;
             const int64_t k = k0 + kk;
             const bool kin = k < k_hi;
-            const int64_t row = r0 + r;
-            pa[u] = (kin && row < r_end) ? Amat[row * lda + k] : T(0);
-            pb[u] = (kin && r < w) ? Yt[(int64_t)r * ldy + k] : T(0);
+            pa[u] = operand_load<T>(
+                ra, (kin && r < arows) ? (uint32_t)(sizeof(T) * (r * lda + k)) : kOutOfRange);
+            pb[u] = operand_load<T>(
+                rb, (kin && r < w) ? (uint32_t)(sizeof(T) * ((int64_t)r * ldy + k)) : kOutOfRange);
         }
     };
     gload(k_lo);
