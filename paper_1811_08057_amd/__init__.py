@@ -345,7 +345,9 @@ class BatchedPlan:
     other.  ``blocked_min_n=None`` keeps every member in the batched
     launch."""
 
-    BLOCKED_MIN_N = 1024
+    # 64 Wishart members n ~ U{256..2048}: 1024 -> 109.6 ms FP64, 1280 -> 95.6,
+    # 1472 -> 72.8, 1536 -> 75.2 (FP32 62.6), 1664 -> 91.0, none -> 148.0
+    BLOCKED_MIN_N = 1536
 
     def __init__(self, mats, b: int = -1, update="native",
                  blocked_min_n: Optional[int] = BLOCKED_MIN_N,

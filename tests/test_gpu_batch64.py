@@ -177,7 +177,7 @@ def test_batch64_backward_sampled_entries_every_member(batch64, precision):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_batch64_batched_autograd_every_member(batch64, precision):
     """The whole batch through the batched autograd function: one batched
-    factor launch (members below 1024 rows) plus single-matrix factor calls,
+    factor launch (members below BatchedPlan.BLOCKED_MIN_N rows) plus single-matrix factor calls,
     and one batched backward launch for all 64 members.  Forward against the
     stored oracle values; every member's 16 stored gradient entries against
     the oracle's inverse (FP64 1e-10, FP32 1e-4 of the member's largest

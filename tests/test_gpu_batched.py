@@ -161,14 +161,14 @@ def test_autotune_produces_valid_table():
 
 
 def test_batched_plan_routes_large_members():
-    """Members of at least BatchedPlan.BLOCKED_MIN_N rows go through the
-    blocked path, the rest through the batched launch: the results land in
+    """Members of at least blocked_min_n rows go through the blocked path,
+    the rest through the batched launch: the results land in
     the members' own order and meet the FP64 bar of the oracle, as with
     every member in the batched launch; a captured replay gives the same."""
     sizes = [300, 1100, 64, 1024, 511]
     mats = [synth.normal(n, 4000 + i) for i, n in enumerate(sizes)]
     devs = to_dev(mats, torch.float64)
-    plan = mc.BatchedPlan(devs)
+    plan = mc.BatchedPlan(devs, blocked_min_n=1024)
     assert plan.large == [1, 3] and plan.small == [0, 2, 4]
     plan.run()
     routed = plan.results()
@@ -219,10 +219,10 @@ def test_batched_plan_concurrent_equals_sequential():
     g = np.random.default_rng(77)
     sizes = [1100, 40, 300, 1030, 700, 5, 1024, 999]
     mats = [torch.from_numpy(synth.wishart_from(g, n)).to(DEV) for n in sizes]
-    seq = mc.BatchedPlan(mats, concurrent=False)
+    seq = mc.BatchedPlan(mats, blocked_min_n=1024, concurrent=False)
     seq.run()
     ref = seq.results()
-    con = mc.BatchedPlan(mats)
+    con = mc.BatchedPlan(mats, blocked_min_n=1024)
     assert con.concurrent
     con.run()
     assert con.results() == ref
