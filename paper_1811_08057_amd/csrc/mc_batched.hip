@@ -432,51 +432,56 @@ __device__ void wg_trsm(Region<T>& r, int64_t n, int64_t s0, int nb, T* Xall)
 }
 
 // Trailing update C[pend:, pend:] <- C[., colsrc] - L U12 with tiles of
-// (32 WT) x (32 WT): 4 wavefronts in 2 x 2, WT x WT MFMA tiles each.  The
+// (32 TM) x (32 TN): 4 wavefronts in 2 x 2, TM x TN MFMA tiles each.  The
 // K loop is double-buffered: chunk c+1 is read into registers (buffer
 // loads, out-of-range entries reading 0, all in flight at once) while chunk
 // c feeds the matrix cores, then parked in the other LDS buffer; the tile's
 // old C is read behind chunk 1's operands, so the epilogue waits on no load.
-template <typename T, int WT>
+template <typename T, int TM, int TN>
 __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
                                T* lds)
 {
     using P = typename MfmaFor<T>::P;
-    constexpr int BT = 32 * WT;
+    constexpr int BM = 32 * TM, BN = 32 * TN;
     constexpr int KC = 16;
-    constexpr int LD = BT + 16;
-    constexpr int PA = (BT * KC + kBT - 1) / kBT; // elements per thread per operand
-    T* As = lds;                // [2][KC][LD]
-    T* Bs = lds + 2 * KC * LD;  // [2][KC][LD]
+    constexpr int LDA = BM + 16, LDB = BN + 16;
+    constexpr int PA = (BM * KC + kBT - 1) / kBT; // elements of A per thread per chunk
+    constexpr int PB = (BN * KC + kBT - 1) / kBT;
+    T* As = lds;                 // [2][KC][LDA]
+    T* Bs = lds + 2 * KC * LDA;  // [2][KC][LDB]
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid >> 1, wn = wid & 1;
     const int cin = lane & 15, kl = lane >> 4;
     const int64_t pend = s0 + nb, M = n - pend;
-    const int64_t tiles = (M + BT - 1) / BT;
+    const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (M + BN - 1) / BN;
     const int nch = (nb + KC - 1) / KC;
     const __amdgpu_buffer_rsrc_t rcs = operand_rsrc(r.colsrc + pend, sizeof(int) * M);
-    for (int64_t t = 0; t < tiles * tiles; ++t) {
-        const int64_t rb = (t / tiles) * BT, cb = (t % tiles) * BT;
+    for (int64_t t = 0; t < tiles_m * tiles_n; ++t) {
+        const int64_t rb = (t / tiles_n) * BM, cb = (t % tiles_n) * BN;
         // the tile's rows of L (M x nb, row stride nb) and of C, and U12's
         // nb rows from the tile's first column (offsets stay below 2^31
         // bytes for any matrix that fits in memory)
-        const int64_t rows = (M - rb) < BT ? (M - rb) : BT;
+        const int64_t rows = (M - rb) < BM ? (M - rb) : BM;
         const __amdgpu_buffer_rsrc_t rl = operand_rsrc(r.L + rb * nb, sizeof(T) * rows * nb);
         const __amdgpu_buffer_rsrc_t ru = operand_rsrc(
             r.W + s0 * r.ldw + pend + cb, sizeof(T) * ((int64_t)(nb - 1) * r.ldw + (M - cb)));
         const __amdgpu_buffer_rsrc_t rcm =
             operand_rsrc(r.W + (pend + rb) * r.ldw, sizeof(T) * rows * r.ldw);
-        T pa[PA], pb[PA];
+        T pa[PA], pb[PB];
         auto gload = [&](int k0) {
 #pragma unroll
             for (int p = 0; p < PA; ++p) {
                 const int e = tid + p * kBT;
                 const int rr = e / KC, kk = e - rr * KC;
-                const bool oka = e < BT * KC && k0 + kk < nb; // rows past M: past the range
+                const bool oka = e < BM * KC && k0 + kk < nb; // rows past M: past the range
                 pa[p] = operand_load<T>(
                     rl, oka ? (uint32_t)(sizeof(T) * (rr * nb + k0 + kk)) : kOutOfRange);
-                const int kb = e / BT, cc = e - kb * BT;
-                const bool okb = e < BT * KC && cb + cc < M && k0 + kb < nb;
+            }
+#pragma unroll
+            for (int p = 0; p < PB; ++p) {
+                const int e = tid + p * kBT;
+                const int kb = e / BN, cc = e - kb * BN;
+                const bool okb = e < BN * KC && cb + cc < M && k0 + kb < nb;
                 pb[p] = operand_load<T>(
                     ru, okb ? (uint32_t)(sizeof(T) * ((int64_t)(k0 + kb) * r.ldw + cc))
                             : kOutOfRange);
@@ -486,44 +491,46 @@ __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
 #pragma unroll
             for (int p = 0; p < PA; ++p) {
                 const int e = tid + p * kBT;
-                if (e < BT * KC) {
-                    const int rr = e / KC, kk = e - rr * KC;
-                    As[(buf * KC + kk) * LD + rr] = -pa[p];
-                    const int kb = e / BT, cc = e - kb * BT;
-                    Bs[(buf * KC + kb) * LD + cc] = pb[p];
-                }
+                const int rr = e / KC, kk = e - rr * KC;
+                if (e < BM * KC) As[(buf * KC + kk) * LDA + rr] = -pa[p];
+            }
+#pragma unroll
+            for (int p = 0; p < PB; ++p) {
+                const int e = tid + p * kBT;
+                const int kb = e / BN, cc = e - kb * BN;
+                if (e < BN * KC) Bs[(buf * KC + kb) * LDB + cc] = pb[p];
             }
         };
-        int csrc[WT];
+        int csrc[TN];
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj) {
-            const int64_t col = cb + wn * 16 * WT + tj * 16 + cin;
+        for (int tj = 0; tj < TN; ++tj) {
+            const int64_t col = cb + wn * 16 * TN + tj * 16 + cin;
             csrc[tj] = (int)__builtin_amdgcn_raw_buffer_load_b32(
                 rcs, col < M ? (uint32_t)(sizeof(int) * col) : kOutOfRange, 0, 0);
         }
         gload(0);
-        typename P::Acc acc[WT][WT];
+        typename P::Acc acc[TM][TN];
 #pragma unroll
-        for (int a = 0; a < WT; ++a)
+        for (int a = 0; a < TM; ++a)
 #pragma unroll
-            for (int b = 0; b < WT; ++b)
+            for (int b = 0; b < TN; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[a][b][q] = T(0);
         sstore(0);
         __syncthreads();
-        T cpre[WT][WT][4];
+        T cpre[TM][TN][4];
         for (int c = 0; c < nch; ++c) {
             const int buf = c & 1;
             if (c + 1 < nch) gload((c + 1) * KC);
             if (c == 0) {
 #pragma unroll
-                for (int tj = 0; tj < WT; ++tj) {
-                    const bool okc = cb + wn * 16 * WT + tj * 16 + cin < M;
+                for (int tj = 0; tj < TN; ++tj) {
+                    const bool okc = cb + wn * 16 * TN + tj * 16 + cin < M;
 #pragma unroll
-                    for (int ti = 0; ti < WT; ++ti)
+                    for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const int rr = wm * 16 * WT + ti * 16 + P::drow(lane, q);
+                            const int rr = wm * 16 * TM + ti * 16 + P::drow(lane, q);
                             cpre[ti][tj][q] = operand_load<T>(
                                 rcm, okc ? (uint32_t)(sizeof(T) * (rr * r.ldw + csrc[tj]))
                                          : kOutOfRange);
@@ -532,16 +539,17 @@ __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
             }
 #pragma unroll
             for (int kq = 0; kq < KC; kq += 4) {
-                T a[WT], b[WT];
+                T a[TM], b[TN];
 #pragma unroll
-                for (int q = 0; q < WT; ++q) {
-                    a[q] = As[(buf * KC + kq + kl) * LD + wm * 16 * WT + q * 16 + cin];
-                    b[q] = Bs[(buf * KC + kq + kl) * LD + wn * 16 * WT + q * 16 + cin];
-                }
+                for (int q = 0; q < TM; ++q)
+                    a[q] = As[(buf * KC + kq + kl) * LDA + wm * 16 * TM + q * 16 + cin];
 #pragma unroll
-                for (int ti = 0; ti < WT; ++ti)
+                for (int q = 0; q < TN; ++q)
+                    b[q] = Bs[(buf * KC + kq + kl) * LDB + wn * 16 * TN + q * 16 + cin];
 #pragma unroll
-                    for (int tj = 0; tj < WT; ++tj)
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
                         acc[ti][tj] = P::mma(a[ti], b[tj], acc[ti][tj]);
             }
             if (c + 1 < nch) sstore(buf ^ 1);
@@ -550,14 +558,14 @@ __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
         // C[dst] = C[src] + acc (a moved column's source lies in the
         // panel's column range, which no tile writes)
 #pragma unroll
-        for (int tj = 0; tj < WT; ++tj) {
-            const int64_t col = cb + wn * 16 * WT + tj * 16 + cin;
+        for (int tj = 0; tj < TN; ++tj) {
+            const int64_t col = cb + wn * 16 * TN + tj * 16 + cin;
             if (col >= M) continue;
 #pragma unroll
-            for (int ti = 0; ti < WT; ++ti)
+            for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int64_t row = rb + wm * 16 * WT + ti * 16 + P::drow(lane, q);
+                    const int64_t row = rb + wm * 16 * TM + ti * 16 + P::drow(lane, q);
                     if (row < M)
                         r.W[(pend + row) * r.ldw + pend + col] = cpre[ti][tj][q] + acc[ti][tj][q];
                 }
@@ -565,6 +573,11 @@ __device__ void wg_gemm_scalar(Region<T>& r, int64_t n, int64_t s0, int nb,
     }
     __syncthreads();
 }
+
+// With a 64-wide tile chosen, trailing blocks of at least this many rows
+// take 128 x 64 tiles (each wavefront 64 x 32: eight accumulators, so more
+// independent products per operand read at one wavefront per SIMD).
+constexpr int64_t kBigTileRows = 512;
 
 // Split-BF16 x 3 form of the trailing update (FP32 storage).
 template <int WT>
@@ -663,10 +676,12 @@ __device__ void wg_trailing<double>(Region<double>& r, int64_t n, int64_t s0,
                                     int nb, int tile, int update, double* lds)
 {
     (void)update;
-    if (tile >= 64)
-        wg_gemm_scalar<double, 2>(r, n, s0, nb, lds);
+    if (tile >= 64 && n - s0 - nb >= kBigTileRows)
+        wg_gemm_scalar<double, 4, 2>(r, n, s0, nb, lds);
+    else if (tile >= 64)
+        wg_gemm_scalar<double, 2, 2>(r, n, s0, nb, lds);
     else
-        wg_gemm_scalar<double, 1>(r, n, s0, nb, lds);
+        wg_gemm_scalar<double, 1, 1>(r, n, s0, nb, lds);
 }
 
 template <>
@@ -679,10 +694,12 @@ __device__ void wg_trailing<float>(Region<float>& r, int64_t n, int64_t s0,
         else
             wg_gemm_bf16x3<1>(r, n, s0, nb, lds);
     } else {
-        if (tile >= 64)
-            wg_gemm_scalar<float, 2>(r, n, s0, nb, lds);
+        if (tile >= 64 && n - s0 - nb >= kBigTileRows)
+            wg_gemm_scalar<float, 4, 2>(r, n, s0, nb, lds);
+        else if (tile >= 64)
+            wg_gemm_scalar<float, 2, 2>(r, n, s0, nb, lds);
         else
-            wg_gemm_scalar<float, 1>(r, n, s0, nb, lds);
+            wg_gemm_scalar<float, 1, 1>(r, n, s0, nb, lds);
     }
 }
 
@@ -867,7 +884,7 @@ size_t batched_lds_bytes(int dtype, const TuneTable& t)
     int64_t bmax = 16;
     for (int k = 0; k < kTuneBuckets; ++k) bmax = std::max<int64_t>(bmax, t.b[k]);
     const size_t trsm = (size_t)elem * 64 * (size_t)(((bmax + 15) / 16) * 16 + 1);
-    const size_t gemm = (size_t)elem * 2 * 2 * 16 * (64 + 16); // A and B, two buffers
+    const size_t gemm = (size_t)elem * 2 * 16 * ((128 + 16) + (64 + 16)); // A and B, two buffers
     const size_t bf16 = 4 * 64 * (32 + 8) * 2;
     return std::max(trsm, std::max(gemm, bf16));
 }
