@@ -1312,14 +1312,26 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
         if (wv == clw / CPW) {
             const int b2 = b * kSplitSlices + slice;
             if (has) {
-                // the column by selects over the wave's columns (a dynamic
-                // register index would move the data to scratch memory)
-                const int cw = clw % CPW;
+                // the column by a register index that every lane shares,
+                // within a vector of at most 32 registers (the largest such
+                // an index reaches without going through memory)
+                constexpr int NV = CPW < 128 / (int)sizeof(T) ? CPW : 128 / (int)sizeof(T);
+                typedef T xvec __attribute__((ext_vector_type(NV)));
+                const int cw = __builtin_amdgcn_readfirstlane(clw % CPW);
+                const int cq = cw / NV, ce = cw % NV;
                 T y0 = T(0), y1 = T(0); // rows 0..63 matter only while k < 63
 #pragma unroll
-                for (int c = 0; c < CPW; ++c) {
-                    if (B0) y0 = (c == cw) ? x[0][c] : y0;
-                    if (H > 1) y1 = (c == cw) ? x[H - 1][c] : y1;
+                for (int q = 0; q < CPW / NV; ++q) {
+                    if (q == cq) {
+                        xvec v0, v1;
+#pragma unroll
+                        for (int e = 0; e < NV; ++e) {
+                            v0[e] = x[0][q * NV + e];
+                            v1[e] = x[H - 1][q * NV + e];
+                        }
+                        if (B0) y0 = v0[ce];
+                        if (H > 1) y1 = v1[ce];
+                    }
                 }
                 const T r = prow[pb][clw];
                 y0 = fma(-mult[pb][lane], r, y0);
@@ -1901,9 +1913,13 @@ __device__ __forceinline__ void wave_lds_sync()
 //     X_J = R_J * inv(U11[J, J])                     (MFMA)
 // with A21[i][t] = W[i][srcp[t]] (the exchanges folded into the load).  X is
 // kept per wavefront in LDS; rows past n and columns past nb are zeros.
+// Only the first `aw` wavefronts of a block take rows (16 each): the gather
+// reads one cache line per entry, and one compute unit keeps only so many
+// lines in flight, so a launch spreads its rows over as many compute units
+// as it can (all four wavefronts still stage U11 and form the inverses).
 template <typename T, bool INV>
 __global__ void __launch_bounds__(kBlkThreads)
-blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
+blk_trsm_mfma(int64_t n, int64_t s0, int nb, int aw, BlkWork<T> w)
 {
     using P = typename MfmaFor<T>::P;
     extern __shared__ unsigned char smem_raw[];
@@ -1914,7 +1930,8 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
     T* X = reinterpret_cast<T*>(smem_raw) + wid * 16 * xld;
     __shared__ int src_sh[kMaxPanel];
     const int64_t pend = s0 + nb;
-    const int64_t i0 = pend + (int64_t)blockIdx.x * kTrsmRows + wid * 16;
+    const int64_t i0 = pend + (int64_t)blockIdx.x * (16 * aw) + wid * 16;
+    const bool rows_here = wid < aw;
     const T* __restrict__ W = w.W;
     const int64_t ldw = w.ldw;
     const T* U = W + s0 * ldw + s0;
@@ -1978,7 +1995,8 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t row = i0 + P::drow(lane, r);
-            g[J][r] = (J < nblk && row < n && t < nb) ? W[row * ldw + src_sh[t]] : T(0);
+            g[J][r] = (rows_here && J < nblk && row < n && t < nb) ? W[row * ldw + src_sh[t]]
+                                                                   : T(0);
         }
     }
     if (INV) {
@@ -2004,6 +2022,7 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, BlkWork<T> w)
         }
         __syncthreads(); // the inverses are in, the solve rows free again
     }
+    if (!rows_here) return;
 #pragma unroll
     for (int J = 0; J < kMaxPanel / 16; ++J) {
         if (J >= nblk) break;
@@ -2299,6 +2318,17 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         if (e != hipSuccess) return note_hip_error(e);
     }
     const bool split_on = g_split_on.load();
+    int cus = 0; // compute units of the device (for the TRSM's spread)
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            cus < 1) {
+            (void)hipGetLastError();
+            cus = 256;
+        }
+    }
     hipLaunchKernelGGL(blk_init<T>, dim3((unsigned)n), dim3(kBlkThreads), 0,
                        stream, A, lda, n, w);
     DevSched* la = lookahead ? ds : nullptr;
@@ -2374,14 +2404,19 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
             pending = false;
         }
         {
-            const dim3 grid((unsigned)((rows + kTrsmRows - 1) / kTrsmRows));
+            // 16-row tiles, up to four a block, as few a block as keeps the
+            // blocks within the compute units
+            const int64_t tiles = (rows + 15) / 16;
+            const int aw = (int)std::min<int64_t>(4, std::max<int64_t>(
+                                                         1, (tiles + cus - 1) / cus));
+            const dim3 grid((unsigned)((tiles + aw - 1) / aw));
             const size_t lds = trsm_mfma_lds_bytes<T>(nb);
             if (split) // inverts U11's diagonal blocks itself
                 hipLaunchKernelGGL((blk_trsm_mfma<T, true>), grid, dim3(kBlkThreads), lds,
-                                   stream, n, s0, nb, wk);
+                                   stream, n, s0, nb, aw, wk);
             else
                 hipLaunchKernelGGL((blk_trsm_mfma<T, false>), grid, dim3(kBlkThreads), lds,
-                                   stream, n, s0, nb, wk);
+                                   stream, n, s0, nb, aw, wk);
         }
         // lookahead, when the next panel is a column-split panel and the
         // device shows all eight XCDs: the next panel's rows first, on the

@@ -463,53 +463,81 @@ gemm_rows(GemmArgs<typename P::T> g)
     const int K = g.K;
     typedef T tv __attribute__((ext_vector_type(V)));
 
-    // the finishing rows of this thread: row fr + 4 q (q = 0..3) of its
-    // wavefront's 16, column fc; their old C (through colsrc) first
+    // Every load goes through a buffer descriptor, entries outside an
+    // operand at an offset past its range (read as zero), so none sits in a
+    // branch and all of them are in flight together.
+    // The finishing rows of this thread: row fr + 4 q (q = 0..3) of its
+    // wavefront's 16, column fc.
     const int fr = wid * 16 + (lane >> 4), fc = (lane & 15) * 4;
-    int64_t src[4];
+    const __amdgpu_buffer_rsrc_t rl =
+        operand_rsrc(g.L, (int64_t)sizeof(T) * ((g.M - 1) * g.ldl + K));
+    const __amdgpu_buffer_rsrc_t ru =
+        operand_rsrc(g.U + g.c0, (int64_t)sizeof(T) * ((int64_t)(K - 1) * g.ldu + g.N));
+    // 16-byte loads where every vector lies wholly inside or wholly outside
+    // its operand and the rows are 16-byte aligned (the blocked path's L and
+    // W are; a caller's matrix need not be): the same for the whole block
+    const bool vec = K % V == 0 && cb + BT <= g.N &&
+                     ((reinterpret_cast<uintptr_t>(g.L) | (uintptr_t)g.ldl * sizeof(T)) & 15) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(g.U + g.c0) | (uintptr_t)g.ldu * sizeof(T)) &
+                      15) == 0;
+    tv pa[PE], pb[PE];
+    if (vec) {
+#pragma unroll
+        for (int p = 0; p < PE; ++p) {
+            const int e = (tid + 256 * p) * V;
+            const int rr = e / KM, kk = e % KM; // L: rows of K contiguous
+            const int64_t row = rb + rr;
+            const uint32_t lo = row < g.M && kk < K
+                                    ? (uint32_t)(sizeof(T) * (row * g.ldl + kk))
+                                    : kOutOfRange;
+            pa[p] = __builtin_bit_cast(tv, __builtin_amdgcn_raw_buffer_load_b128(rl, lo, 0, 0));
+            const int kb = e / BT, cc = e % BT; // U: K rows of 64 columns
+            const uint32_t uo = kb < K ? (uint32_t)(sizeof(T) * ((int64_t)kb * g.ldu + cb + cc))
+                                       : kOutOfRange;
+            pb[p] = __builtin_bit_cast(tv, __builtin_amdgcn_raw_buffer_load_b128(ru, uo, 0, 0));
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < PE; ++p) {
+            const int e = (tid + 256 * p) * V;
+            const int rr = e / KM, kk = e % KM;
+            const int64_t row = rb + rr;
+            const int kb = e / BT, cc = e % BT;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const uint32_t lo = row < g.M && kk + v < K
+                                        ? (uint32_t)(sizeof(T) * (row * g.ldl + kk + v))
+                                        : kOutOfRange;
+                pa[p][v] = operand_load<T>(rl, lo);
+                const int64_t col = cb + cc + v;
+                const uint32_t uo = kb < K && col < g.N
+                                        ? (uint32_t)(sizeof(T) * ((int64_t)kb * g.ldu + col))
+                                        : kOutOfRange;
+                pb[p][v] = operand_load<T>(ru, uo);
+            }
+        }
+    }
+    const __amdgpu_buffer_rsrc_t rcs = operand_rsrc(g.colsrc + g.c0, sizeof(int) * g.N);
+    int src[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int64_t col = cb + fc + q;
-        src[q] = col < g.N ? g.colsrc[g.c0 + col] : 0;
+        src[q] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+            rcs, col < g.N ? (uint32_t)(sizeof(int) * col) : kOutOfRange, 0, 0);
     }
-    // 16-byte loads where the rows are 16-byte aligned (the blocked path's
-    // L and W are; a caller's matrix need not be)
-    const bool lvec = ((reinterpret_cast<uintptr_t>(g.L) |
-                        (uintptr_t)g.ldl * sizeof(T)) & 15) == 0;
-    const bool uvec = ((reinterpret_cast<uintptr_t>(g.U + g.c0) |
-                        (uintptr_t)g.ldu * sizeof(T)) & 15) == 0;
-    tv pa[PE], pb[PE];
-#pragma unroll
-    for (int p = 0; p < PE; ++p) {
-        const int e = (tid + 256 * p) * V;
-        const int rr = e / KM, kk = e % KM; // L: rows of K contiguous
-        const int64_t row = rb + rr;
-        if (lvec && row < g.M && kk + V <= K) {
-            pa[p] = *reinterpret_cast<const tv*>(g.L + row * g.ldl + kk);
-        } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                pa[p][v] = (row < g.M && kk + v < K) ? g.L[row * g.ldl + kk + v] : T(0);
-        }
-        const int kb = e / BT, cc = e % BT; // U: K rows of 64 columns
-        const int64_t col = cb + cc;
-        const T* up = g.U + (int64_t)kb * g.ldu + g.c0 + col;
-        if (uvec && kb < K && col + V <= g.N) {
-            pb[p] = *reinterpret_cast<const tv*>(up);
-        } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) pb[p][v] = (kb < K && col + v < g.N) ? up[v] : T(0);
-        }
-    }
+    // the old C through colsrc (rows past M and columns past N read zero)
+    const __amdgpu_buffer_rsrc_t rc =
+        operand_rsrc(g.C + g.r0 * g.ldc, (int64_t)sizeof(T) * g.M * g.ldc);
     T cold[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int64_t row = rb + fr + 4 * r;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            cold[r][q] = (row < g.M && cb + fc + q < g.N)
-                             ? g.C[(g.r0 + row) * g.ldc + src[q]]
-                             : T(0);
+            cold[r][q] = operand_load<T>(
+                rc, row < g.M && cb + fc + q < g.N
+                        ? (uint32_t)(sizeof(T) * (row * g.ldc + src[q]))
+                        : kOutOfRange);
     }
 #pragma unroll
     for (int p = 0; p < PE; ++p) {
