@@ -40,7 +40,6 @@
 namespace mc {
 
 constexpr int kBlkThreads = 256;
-constexpr int kTrsmRows = 64; // rows per solve block (16 per wavefront)
 
 template <typename T>
 __global__ void __launch_bounds__(kBlkThreads)
@@ -1898,21 +1897,16 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
     }
 }
 
-// Order a wavefront's LDS accesses around this point for the compiler (no
-// instruction: the hardware already completes them in order).
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// L21 = A21 * U11^{-1} on the matrix cores, one wavefront per 16 rows, in
-// 16-column blocks J (forward substitution by blocks):
-//     R_J = A21[:, J] - sum_{K<J} X_K U11[K, J]      (MFMA, K = 16 per block)
-//     X_J = R_J * inv(U11[J, J])                     (MFMA)
-// with A21[i][t] = W[i][srcp[t]] (the exchanges folded into the load).  X is
-// kept per wavefront in LDS; rows past n and columns past nb are zeros.
+// L21 = A21 * U11^{-1} on the matrix cores, one wavefront per 16 rows, as
+// its transpose X^T = U11^{-T} A21^T in 16-row blocks J of X^T (forward
+// substitution by blocks):
+//     R_J = A21^T[J, :] - sum_{K<J} U11[K, J]^T X^T[K, :]   (MFMA, K = 16 per block)
+//     X^T[J, :] = inv(U11[J, J])^T R_J                      (MFMA)
+// with A21[i][t] = W[i][srcp[t]] (the exchanges folded into the load).  In
+// this form a finished block, in the accumulator layout, is already the
+// second operand of the later blocks' products: the rows of X^T a lane
+// holds are the k values it supplies, so X never leaves the registers.
+// Rows past n and columns past nb are zeros.
 // Only the first `aw` wavefronts of a block take rows (16 each): the gather
 // reads one cache line per entry, and one compute unit keeps only so many
 // lines in flight, so a launch spreads its rows over as many compute units
@@ -1924,10 +1918,8 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, int aw, BlkWork<T> w)
     using P = typename MfmaFor<T>::P;
     extern __shared__ unsigned char smem_raw[];
     const int nblk = (nb + 15) / 16;
-    const int xld = nblk * 16 + 1;
     if (w.state->status != kStatusOk) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    T* X = reinterpret_cast<T*>(smem_raw) + wid * 16 * xld;
     __shared__ int src_sh[kMaxPanel];
     const int64_t pend = s0 + nb;
     const int64_t i0 = pend + (int64_t)blockIdx.x * (16 * aw) + wid * 16;
@@ -1935,7 +1927,7 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, int aw, BlkWork<T> w)
     const T* __restrict__ W = w.W;
     const int64_t ldw = w.ldw;
     const T* U = W + s0 * ldw + s0;
-    const int cin = lane & 15, kl = lane >> 4;
+    const int cin = lane & 15;
     // U11's strictly upper 16x16 blocks (K < J at tri(K, J) = J(J-1)/2 + K)
     // and the inverted diagonal blocks, both in LDS: the solve's chain then
     // waits on no global load.
@@ -1943,7 +1935,7 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, int aw, BlkWork<T> w)
     constexpr int kMaxTri = kMaxBlk * (kMaxBlk - 1) / 2;
     static_assert(kBlkThreads == 256, "one 16x16 block element per thread");
     const int ntri = nblk * (nblk - 1) / 2;
-    T* Ub = reinterpret_cast<T*>(smem_raw) + kTrsmRows * xld;
+    T* Ub = reinterpret_cast<T*>(smem_raw) + kMaxBlk * 272; // after the staging
     T* Dv = Ub + ntri * 256;
     for (int t = tid; t < nb; t += kBlkThreads) src_sh[t] = w.srcp[t];
     if (INV && blockIdx.x == 0 && tid == 0) { // after a column-split panel:
@@ -1980,23 +1972,26 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, int aw, BlkWork<T> w)
 #pragma unroll
         for (int J = 0; J < kMaxBlk; ++J)
             if (J < nblk) {
-                if (INV) // the blocks go to the (still unused) solve rows
+                if (INV) // the blocks, padded, for the inverses below
                     reinterpret_cast<T*>(smem_raw)[J * 272 + er * 17 + ec] = st[kMaxTri + J];
                 else
                     Dv[J * 256 + tid] = st[kMaxTri + J];
             }
     }
     __syncthreads();
-    // every gathered entry of A21 first (one memory latency for all blocks)
+    // every gathered entry of A21 first (one memory latency for all
+    // blocks): lane (cin, r) of block J takes row i0 + cin, column
+    // 16 J + P::drow(lane, r), in the accumulator layout of X^T
     T g[kMaxBlk][4];
+    const int64_t grow = i0 + cin;
 #pragma unroll
     for (int J = 0; J < kMaxBlk; ++J) {
-        const int t = 16 * J + cin;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t row = i0 + P::drow(lane, r);
-            g[J][r] = (rows_here && J < nblk && row < n && t < nb) ? W[row * ldw + src_sh[t]]
-                                                                   : T(0);
+            const int t = 16 * J + P::drow(lane, r);
+            g[J][r] = (rows_here && J < nblk && grow < n && t < nb)
+                          ? W[grow * ldw + src_sh[t]]
+                          : T(0);
         }
     }
     if (INV) {
@@ -2020,46 +2015,45 @@ blk_trsm_mfma(int64_t n, int64_t s0, int nb, int aw, BlkWork<T> w)
 #pragma unroll
             for (int r = 0; r < 16; ++r) Dv[(J * 16 + r) * 16 + c] = x[r];
         }
-        __syncthreads(); // the inverses are in, the solve rows free again
+        __syncthreads(); // the inverses are in
     }
     if (!rows_here) return;
+    typename P::Acc xt[kMaxBlk]; // finished blocks of X^T
 #pragma unroll
-    for (int J = 0; J < kMaxPanel / 16; ++J) {
+    for (int J = 0; J < kMaxBlk; ++J) {
         if (J >= nblk) break;
         typename P::Acc acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = g[J][r];
-        for (int K = 0; K < J; ++K) {
 #pragma unroll
-            for (int kq = 0; kq < 4; ++kq) {
-                const int k = 16 * K + 4 * kq + kl; // k < 16 J <= t
-                const T a = -X[cin * xld + k];
-                const T b = Ub[(J * (J - 1) / 2 + K) * 256 + (4 * kq + kl) * 16 + cin];
-                acc = P::mma(a, b, acc);
+        for (int K = 0; K < kMaxBlk; ++K) {
+            if (K >= J) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // k = P::drow(lane, q): row k of block K of X^T is this
+                // lane's register q; A supplies U11[16 K + k][16 J + cin]
+                const T a = -Ub[(J * (J - 1) / 2 + K) * 256 + P::drow(lane, q) * 16 + cin];
+                acc = P::mma(a, xt[K][q], acc);
             }
         }
-        // X is this wavefront's own (the other LDS data is read-only here):
-        // a wavefront's LDS accesses complete in order, so ordering them for
-        // the compiler is all the synchronisation needed
-#pragma unroll
-        for (int r = 0; r < 4; ++r) X[P::drow(lane, r) * xld + 16 * J + cin] = acc[r];
-        wave_lds_sync();
         typename P::Acc x = {0, 0, 0, 0};
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-            const T a = X[cin * xld + 16 * J + 4 * kq + kl];
-            const T b = Dv[(J * 16 + 4 * kq + kl) * 16 + cin];
-            x = P::mma(a, b, x);
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) X[P::drow(lane, r) * xld + 16 * J + cin] = x[r];
-        wave_lds_sync();
+        for (int q = 0; q < 4; ++q) // inv(U_JJ)[k][cin] against row k of R_J
+            x = P::mma(Dv[(J * 16 + P::drow(lane, q)) * 16 + cin], acc[q], x);
+        xt[J] = x;
     }
-    for (int e = lane; e < 16 * nb; e += kWave) {
-        const int ii = e / nb, tt = e - ii * nb;
-        const int64_t row = i0 + ii;
-        if (row < n) w.L[(row - pend) * w.ldl + tt] = X[ii * xld + tt];
+    // L21[i0 + cin][16 J + P::drow(lane, r)] = X^T[...][cin]
+    if (grow < n) {
+        T* lrow = w.L + (grow - pend) * w.ldl;
+#pragma unroll
+        for (int J = 0; J < kMaxBlk; ++J) {
+            if (J >= nblk) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = 16 * J + P::drow(lane, r);
+                if (t < nb) lrow[t] = xt[J][r];
+            }
+        }
     }
 }
 
@@ -2176,8 +2170,9 @@ static size_t trsm_mfma_lds_bytes(int nb)
 {
     const int nblk = (nb + 15) / 16;
     const int ntri = nblk * (nblk - 1) / 2; // strictly upper 16x16 blocks of U11
-    return sizeof(T) * ((size_t)(kTrsmRows) * (size_t)(nblk * 16 + 1) +
-                        (size_t)(ntri + nblk) * 256);
+    // the diagonal blocks' staging (8 of 16 x 17), then U11's strictly upper
+    // blocks and the inverted diagonal blocks
+    return sizeof(T) * ((size_t)(kMaxPanel / 16) * 272 + (size_t)(ntri + nblk) * 256);
 }
 
 // ---- per-device scheduling: one-panel lookahead, and calls one at a time ----

@@ -446,14 +446,19 @@ gemm_rows(GemmArgs<typename P::T> g)
 {
     using T = typename P::T;
     constexpr int BT = 64, KM = (int)kMaxPanel;
-    constexpr int LD = BT + (sizeof(T) == 8 ? 8 : 16); // both tiles in 160 KB
-    constexpr int V = 16 / sizeof(T);                  // elements per 16 bytes
-    constexpr int PE = BT * KM / (256 * V);            // 16-byte loads per tile
-    constexpr int RL = BT + (sizeof(T) == 8 ? 2 : 4);  // partial-tile row pitch
-    static_assert(4 * BT * RL <= 2 * KM * LD, "partials fit in the operand space");
-    __shared__ T lds[2 * KM * LD];
-    T (*As)[LD] = reinterpret_cast<T (*)[LD]>(lds);           // -L, k major
-    T (*Bs)[LD] = reinterpret_cast<T (*)[LD]>(lds + KM * LD); // U
+    constexpr int LD = BT + (sizeof(T) == 8 ? 8 : 16); // U's row pitch
+    constexpr int LK = KM + 4;                          // -L's row pitch
+    constexpr int V = 16 / sizeof(T);                   // elements per 16 bytes
+    constexpr int PE = BT * KM / (256 * V);             // 16-byte loads per tile
+    constexpr int RL = BT + (sizeof(T) == 8 ? 2 : 4);   // partial-tile row pitch
+    constexpr int NL = BT * LK + KM * LD;               // both tiles, within 160 KB
+    static_assert(4 * BT * RL <= NL, "partials fit in the operand space");
+    __shared__ T lds[NL];
+    // -L row major (a row's K entries contiguous, so a wavefront's 16-byte
+    // stores cover whole rows; the pad spreads the fragment reads, 16 rows
+    // by 4 k, over the banks), U k major
+    T (*As)[LK] = reinterpret_cast<T (*)[LK]>(lds);
+    T (*Bs)[LD] = reinterpret_cast<T (*)[LD]>(lds + BT * LK);
     if (g.state->status != kStatusOk) return;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -544,7 +549,7 @@ gemm_rows(GemmArgs<typename P::T> g)
         const int e = (tid + 256 * p) * V;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            As[(e + v) % KM][(e + v) / KM] = -pa[p][v];
+            As[(e + v) / KM][(e + v) % KM] = -pa[p][v];
             Bs[(e + v) / BT][(e + v) % BT] = pb[p][v];
         }
     }
@@ -564,7 +569,7 @@ gemm_rows(GemmArgs<typename P::T> g)
         T a[4], b[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            a[t] = As[kq + kq_lane][t * 16 + col_in];
+            a[t] = As[t * 16 + col_in][kq + kq_lane];
             b[t] = Bs[kq + kq_lane][t * 16 + col_in];
         }
 #pragma unroll
