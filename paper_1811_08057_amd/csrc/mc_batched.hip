@@ -373,62 +373,153 @@ __device__ void wg_perm(Region<T>& r, int64_t n, int64_t s0, int nb)
     __syncthreads();
 }
 
-// L21 = gather(A21) * U11^{-1}, 64 rows per pass (16 per wavefront), as
-// blk_trsm_mfma.  X: LDS, 4 x 16 x (nblk*16 + 1) elements.
-template <typename T>
-__device__ void wg_trsm(Region<T>& r, int64_t n, int64_t s0, int nb, T* Xall)
+// L21 = A21 * U11^{-1} for the rows below the panel on the matrix cores,
+// as its transpose X^T = U11^{-T} A21^T in 16-row blocks J of X^T:
+//     R_J = A21^T[J, :] - sum_{K<J} U11[K, J]^T X^T[K, :]
+//     X^T[J, :] = inv(U11[J, J])^T R_J
+// (A21[i][t] = W[i][srcp[t]], the exchanges folded into the load).  Each
+// wavefront takes 16 rows at a time; a finished block, in the accumulator
+// layout, is already the second operand of the later blocks' products (the
+// rows of X^T a lane holds are the k values it supplies), so X never leaves
+// the registers and the row loop has no barrier.  U11's strictly upper
+// 16 x 16 blocks, the inverted diagonal blocks (wg_perm) and the columns'
+// sources are staged in LDS first; A21's entries come through a buffer
+// descriptor (rows past n read zero), all of a row group's in flight
+// together.  MB: the most 16-column blocks the panel may have.
+template <typename T, int MB>
+__device__ void wg_trsm_blocks(Region<T>& r, int64_t n, int64_t s0, int nb, T* lds)
 {
     using P = typename MfmaFor<T>::P;
+    constexpr int kTri = MB * (MB - 1) / 2;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nblk = (nb + 15) / 16;
-    const int xld = nblk * 16 + 1;
-    T* X = Xall + wid * 16 * xld;
-    const int64_t pend = s0 + nb;
-    const T* W = r.W;
+    const int ntri = nblk * (nblk - 1) / 2;
+    T* Ub = lds;                 // block (K, J), K < J, at tri(K, J) = J (J - 1) / 2 + K
+    T* Dv = lds + ntri * 256;    // inv(U11[J, J]), row-major per block
+    int* src = reinterpret_cast<int*>(Dv + nblk * 256); // 16 nblk sources
+    const int64_t pend = s0 + nb, m = n - pend;
     const int64_t ldw = r.ldw;
-    const T* U = W + s0 * ldw + s0;
-    const int cin = lane & 15, kl = lane >> 4;
-    for (int64_t g0 = pend; g0 < n; g0 += 64) {
-        const int64_t i0 = g0 + wid * 16;
-        for (int J = 0; J < nblk; ++J) {
-            const int t = 16 * J + cin;
-            typename P::Acc acc;
+    const int cin = lane & 15;
+    {
+        const int er = tid >> 4, ec = tid & 15;
+        const __amdgpu_buffer_rsrc_t ru = operand_rsrc(
+            r.W + s0 * ldw + s0, (int64_t)sizeof(T) * ((int64_t)(nb - 1) * ldw + nb));
+        // item u < kTri: upper block tri(K, J) = u; else diagonal block
+        // u - kTri; in chunks of CH items (loads of a chunk in flight
+        // together, the chunks one after another: the registers hold one)
+        constexpr int NI = kTri + MB, CH = NI <= 12 ? NI : 9;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t row = i0 + P::drow(lane, q);
-                acc[q] = (row < n && t < nb) ? W[row * ldw + r.srcp[t]] : T(0);
-            }
-            for (int K = 0; K < J; ++K) {
+        for (int c0 = 0; c0 < NI; c0 += CH) {
+            T v[CH];
 #pragma unroll
-                for (int kq = 0; kq < 4; ++kq) {
-                    const int k = 16 * K + 4 * kq + kl;
-                    const T a = -X[cin * xld + k];
-                    const T b = (t < nb) ? U[(int64_t)k * ldw + t] : T(0);
-                    acc = P::mma(a, b, acc);
+            for (int u = 0; u < CH; ++u) {
+                const int it = c0 + u;
+                if (it >= NI) break;
+                if (it < kTri) {
+                    int J = 1;
+                    while (J * (J + 1) / 2 <= it) ++J; // tri(K, J) = it
+                    const int K = it - J * (J - 1) / 2, t = 16 * J + ec;
+                    // row 16 K + er < nb whenever K < J < nblk
+                    v[u] = operand_load<T>(
+                        ru, (J < nblk && t < nb)
+                                ? (uint32_t)(sizeof(T) * ((16 * K + er) * ldw + t))
+                                : kOutOfRange);
+                } else {
+                    const int J = it - kTri;
+                    v[u] = J < nblk ? r.dinv[J * 256 + tid] : T(0);
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) X[P::drow(lane, q) * xld + 16 * J + cin] = acc[q];
-            __syncthreads();
+            for (int u = 0; u < CH; ++u) {
+                const int it = c0 + u;
+                if (it >= NI) break;
+                if (it < kTri) {
+                    int J = 1;
+                    while (J * (J + 1) / 2 <= it) ++J;
+                    if (J < nblk) Ub[it * 256 + tid] = v[u];
+                } else if (it - kTri < nblk) {
+                    Dv[(it - kTri) * 256 + tid] = v[u];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (tid < 16 * nblk) src[tid] = tid < nb ? r.srcp[tid] : 0;
+    }
+    __syncthreads();
+    for (int64_t g0 = 0; g0 < m; g0 += 64) {
+        // lane (cin, q) of block J: row g0 + li (from pend), column
+        // 16 J + P::drow(lane, q); one descriptor per group of 64 rows keeps
+        // the offsets small for any matrix
+        const int li = wid * 16 + cin;
+        const int64_t i = g0 + li;
+        const bool rin = i < m;
+        const __amdgpu_buffer_rsrc_t ra = operand_rsrc(
+            r.W + (pend + g0) * ldw, (int64_t)sizeof(T) * (m - g0 < 64 ? m - g0 : 64) * ldw);
+        // up to 4 blocks, every entry first; beyond (panels wider than 64
+        // columns, only on request) each block's entries at that block, so
+        // that the registers hold one block of them
+        constexpr bool kAll = MB <= 4;
+        auto gather = [&](int J, T* gj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 16 * J + P::drow(lane, q);
+                gj[q] = operand_load<T>(
+                    ra, (rin && J < nblk && t < nb)
+                            ? (uint32_t)(sizeof(T) * ((int64_t)li * ldw + src[t]))
+                            : kOutOfRange);
+            }
+        };
+        T g[kAll ? MB : 1][4];
+        if (kAll) {
+#pragma unroll
+            for (int J = 0; J < MB; ++J) gather(J, g[kAll ? J : 0]);
+        }
+        typename P::Acc xt[MB];
+#pragma unroll
+        for (int J = 0; J < MB; ++J) {
+            if (J >= nblk) break;
+            if (!kAll) gather(J, g[0]);
+            typename P::Acc acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = g[kAll ? J : 0][q];
+#pragma unroll
+            for (int K = 0; K < MB; ++K) {
+                if (K >= J) break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T a = -Ub[(J * (J - 1) / 2 + K) * 256 + P::drow(lane, q) * 16 + cin];
+                    acc = P::mma(a, xt[K][q], acc);
+                }
+            }
             typename P::Acc x = {0, 0, 0, 0};
 #pragma unroll
-            for (int kq = 0; kq < 4; ++kq) {
-                const T a = X[cin * xld + 16 * J + 4 * kq + kl];
-                const T b = r.dinv[(J * 16 + 4 * kq + kl) * 16 + cin];
-                x = P::mma(a, b, x);
-            }
-            __syncthreads();
+            for (int q = 0; q < 4; ++q)
+                x = P::mma(Dv[(J * 16 + P::drow(lane, q)) * 16 + cin], acc[q], x);
+            xt[J] = x;
+        }
+        if (rin) {
+            T* lrow = r.L + i * nb;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) X[P::drow(lane, q) * xld + 16 * J + cin] = x[q];
-            __syncthreads();
+            for (int J = 0; J < MB; ++J) {
+                if (J >= nblk) break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t = 16 * J + P::drow(lane, q);
+                    if (t < nb) lrow[t] = xt[J][q];
+                }
+            }
         }
-        for (int e = lane; e < 16 * nb; e += kWave) {
-            const int ii = e / nb, tt = e - ii * nb;
-            const int64_t row = i0 + ii;
-            if (row < n) r.L[(row - pend) * nb + tt] = X[ii * xld + tt];
-        }
-        __syncthreads();
     }
+    __syncthreads(); // the LDS is the trailing update's next
+}
+
+template <typename T>
+__device__ void wg_trsm(Region<T>& r, int64_t n, int64_t s0, int nb, T* lds)
+{
+    if (nb <= 64)
+        wg_trsm_blocks<T, 4>(r, n, s0, nb, lds);
+    else
+        wg_trsm_blocks<T, (int)(kMaxPanel / 16)>(r, n, s0, nb, lds);
 }
 
 // Trailing update C[pend:, pend:] <- C[., colsrc] - L U12 with tiles of
@@ -883,7 +974,9 @@ size_t batched_lds_bytes(int dtype, const TuneTable& t)
     const int elem = dtype == MC_DTYPE_F64 ? 8 : 4;
     int64_t bmax = 16;
     for (int k = 0; k < kTuneBuckets; ++k) bmax = std::max<int64_t>(bmax, t.b[k]);
-    const size_t trsm = (size_t)elem * 64 * (size_t)(((bmax + 15) / 16) * 16 + 1);
+    const int64_t nblk = (bmax + 15) / 16; // U11's upper and inverted diagonal blocks
+    const size_t trsm = (size_t)elem * (size_t)(nblk * (nblk - 1) / 2 + nblk) * 256 +
+                        sizeof(int) * 16 * (size_t)nblk;
     const size_t gemm = (size_t)elem * 2 * 16 * ((128 + 16) + (64 + 16)); // A and B, two buffers
     const size_t bf16 = 4 * 64 * (32 + 8) * 2;
     return std::max(trsm, std::max(gemm, bf16));
