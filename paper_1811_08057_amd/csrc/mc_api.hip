@@ -176,7 +176,7 @@ static size_t blocked_bytes(int64_t n, int dtype, int64_t b, bool with_w)
     t += 4 * align_up(sizeof(int) * (size_t)kMaxPanel, kAlign); // srcp, moved x2
     t += align_up(elem * (size_t)kMaxPanel * 16, kAlign);       // dinv
     t += align_up(sizeof(int) * (size_t)kMaxPanel, kAlign);     // stepflag
-    t += align_up(8 * sizeof(int), kAlign);                     // claim
+    t += align_up(3 * sizeof(int), kAlign);                     // claim
     t += align_up(sizeof(unsigned long long) * 4 * kSplitSlices, kAlign); // xrec
     t += align_up(elem * 2 * kSplitSlices * (size_t)kMaxPanel, kAlign);  // xcol
     t += align_up(sizeof(DevState), kAlign);
@@ -216,7 +216,7 @@ BlkWork<T> blocked_carve(void* work, int64_t n, int64_t b, bool with_w)
     w.moved_b = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
     w.dinv = reinterpret_cast<T*>(take(sizeof(T) * (size_t)kMaxPanel * 16));
     w.stepflag = reinterpret_cast<int*>(take(sizeof(int) * (size_t)kMaxPanel));
-    w.claim = reinterpret_cast<int*>(take(8 * sizeof(int)));
+    w.claim = reinterpret_cast<int*>(take(3 * sizeof(int)));
     w.xrec = reinterpret_cast<unsigned long long*>(
         take(sizeof(unsigned long long) * 4 * kSplitSlices));
     w.xcol = reinterpret_cast<T*>(take(sizeof(T) * 2 * kSplitSlices * (size_t)kMaxPanel));

@@ -68,8 +68,6 @@ blk_init(const T* __restrict__ A, int64_t lda, int64_t n, BlkWork<T> w)
             w.claim[0] = 0;
             w.claim[1] = -1;
             w.claim[2] = 0;
-            w.claim[4] = 0; // the two streams' flags (launch_blocked)
-            w.claim[5] = 0;
         }
     }
 }
@@ -1164,10 +1162,6 @@ blk_panel_split(int64_t n64, int64_t s064, int nb, int nslices, int on_xcc0, Blk
     const int n = (int)n64, s0 = (int)s064, width = n - s0;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // beside an update: this panel has started, so every kernel before it
-    // on its stream has finished and its stores are visible device-wide;
-    // the side stream's update waits for this
-    if (on_xcc0 && blockIdx.x == 0 && tid == 0) st_agent(&w.claim[4], s0 + 1);
     if (tid == 0) {
         // block 0 publishes its XCD (or, beside a trailing update that
         // leaves it alone, the XCD is 0); blocks elsewhere leave, the
@@ -1903,33 +1897,6 @@ blk_perm(int64_t s0, int nb, BlkWork<T> w)
     }
 }
 
-// Ordering between the caller's stream and the side stream of a blocked
-// call without an event each way per panel.  A flag written by a kernel as
-// it starts says that every kernel before it on its stream has finished
-// (with its stores visible device-wide); blk_wait_flag holds its own stream
-// until the flag reaches target, within the bounded wait.  One wavefront:
-// it fits beside any block, so it never keeps the kernels it waits for
-// from running.
-__global__ void __launch_bounds__(64)
-blk_wait_flag(const int* flag, int target, DevState* st)
-{
-    if (threadIdx.x != 0) return;
-    const uint64_t t0 = now_ticks();
-    while (ld_agent(flag) < target) {
-        if (now_ticks() - t0 > kWaitTicks) {
-            st_agent(&st->status, (int)kStatusAborted);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-}
-
-__global__ void __launch_bounds__(64)
-blk_set_flag(int* flag, int value)
-{
-    if (threadIdx.x == 0) st_agent(flag, value);
-}
-
 // L21 = A21 * U11^{-1} on the matrix cores, one wavefront per 16 rows, as
 // its transpose X^T = U11^{-T} A21^T in 16-row blocks J of X^T (forward
 // substitution by blocks):
@@ -2362,7 +2329,6 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
     DevSched* la = lookahead ? ds : nullptr;
     bool pending = false; // side-stream work the caller's stream must join
     bool beside = false;  // ... and it leaves XCD 0 to the next panel
-    bool forked = false;  // the side stream has joined this call
     // rows of the panel starting at s0: b, except that FP64 panels wider
     // than one XCD holds at 32 columns per wavefront (8192) take at most 64
     // rows, so that the column-split panel holds 64 columns per wavefront
@@ -2428,8 +2394,8 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
             hipLaunchKernelGGL(blk_perm<T>, dim3(1), dim3(kBlkThreads), 0, stream,
                                s0, nb, wk);
         if (pending) { // the previous panel's update of the rows below
-            hipLaunchKernelGGL(blk_wait_flag, dim3(1), dim3(64), 0, stream, &w.claim[5],
-                               (int)s0 + 1, w.state);
+            const hipError_t e = hipStreamWaitEvent(stream, la->join, 0);
+            if (e != hipSuccess) return note_hip_error(e);
             pending = false;
         }
         {
@@ -2462,20 +2428,10 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
         if (e != hipSuccess) return e;
         hipStream_t rest = stream;
         if (beside) {
-            // the side stream joins the call once (after blk_init zeroed
-            // the flags); from then on each update starts when the next
-            // panel has (claim[4], written by that panel as it starts), and
-            // the caller's stream takes up the next solve once the side's
-            // kernels for this panel have ended (claim[5], below)
-            if (!forked) {
-                if ((e = hipEventRecord(la->fork, stream)) != hipSuccess ||
-                    (e = hipStreamWaitEvent(la->side, la->fork, 0)) != hipSuccess)
-                    return note_hip_error(e);
-                forked = true;
-            }
+            if ((e = hipEventRecord(la->fork, stream)) != hipSuccess ||
+                (e = hipStreamWaitEvent(la->side, la->fork, 0)) != hipSuccess)
+                return note_hip_error(e);
             rest = la->side;
-            hipLaunchKernelGGL(blk_wait_flag, dim3(1), dim3(64), 0, rest, &w.claim[4],
-                               (int)pend + 1, w.state);
             e = trailing(wk, update, s0, nb, pend + next, rows - next, n, rest,
                          reinterpret_cast<unsigned int*>(&w.claim[2]));
             if (e != hipSuccess) return e;
@@ -2488,18 +2444,15 @@ hipError_t launch_blocked(const T* A, int64_t n, int64_t lda, int64_t b,
                                    dim3((unsigned)((s0 + 3) / 4)),
                                    dim3(kBlkThreads), 0, rest, s0, nb, wk);
         }
-        if (rest != stream) { // the side's kernels for this panel have ended
-            hipLaunchKernelGGL(blk_set_flag, dim3(1), dim3(64), 0, rest, &w.claim[5],
-                               (int)pend + 1);
+        if (rest != stream) {
+            if ((e = hipEventRecord(la->join, rest)) != hipSuccess) return note_hip_error(e);
             pending = true;
         }
         s0 = pend;
     }
-    if (forked) { // the side stream rejoins the call
-        hipError_t e;
-        if ((e = hipEventRecord(la->join, la->side)) != hipSuccess ||
-            (e = hipStreamWaitEvent(stream, la->join, 0)) != hipSuccess)
-            return note_hip_error(e);
+    if (pending) {
+        const hipError_t e = hipStreamWaitEvent(stream, la->join, 0);
+        if (e != hipSuccess) return note_hip_error(e);
     }
     // the last panel (no rows below): its exchanges still reach the rows
     // above it in factor mode

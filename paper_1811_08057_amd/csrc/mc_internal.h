@@ -57,8 +57,7 @@ struct BlkWork {
     int* moved_b;
     T* dinv;       // inverses of the 16 x 16 diagonal blocks of U11
     int* stepflag; // per panel step: 1 once its pivot row is published
-    int* claim;    // [0] panel slot/slice counter, [1] elected XCD, [2] trailing-update tile counter,
-                   // [4] the latest panel started beside an update, [5] the side stream's latest panel done
+    int* claim;    // [0] panel slot/slice counter, [1] elected XCD, [2] trailing-update tile counter
     // column-split panel: per step parity and slice, a 16-byte pivot
     // candidate record and the candidate's column of the panel rows
     unsigned long long* xrec; // [2][kSplitSlices][2]
