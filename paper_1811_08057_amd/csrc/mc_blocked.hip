@@ -20,13 +20,17 @@
 // right of s.  The exchanges are applied to the panel rows as they happen
 // and folded into the loads of the rows below (no separate swap pass).
 //
-// Per panel (b steps, one kernel each, plus four kernels):
-//   blk_head   argmax + factoring of the panel's first row
-//   blk_step   one step on the panel rows; the block owning the next panel
-//              row also finds and factors the next pivot (lookahead)
-//   blk_perm   source position of every column the exchanges moved
+// Per panel:
+//   blk_panel_split  all b steps on one XCD, the panel's columns split over
+//              its compute units (the default while the width fits: 8192
+//              columns for FP64 panels of 128 rows, 16384 otherwise);
+//              otherwise a row-per-block chain (blk_head_r + blk_panel_x or
+//              blk_panel, then blk_fixup_x / blk_fixup and blk_perm), or one
+//              launch per step (blk_head, blk_step)
 //   blk_trsm_mfma  L21 = gather(A21) * U11^{-1} on the matrix cores
-//   gemm       A22 <- gather(A22) - L21 * U12    (mc_gemm.hip)
+//   gemm       A22 <- gather(A22) - L21 * U12 (mc_gemm.hip): with lookahead
+//              the next panel's rows first, the rest on a side stream beside
+//              the next panel
 #include <algorithm>
 #include <type_traits>
 #include <atomic>
