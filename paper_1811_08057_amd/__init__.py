@@ -345,8 +345,9 @@ class BatchedPlan:
     other.  ``blocked_min_n=None`` keeps every member in the batched
     launch."""
 
-    # 64 Wishart members n ~ U{256..2048}: 1024 -> 109.6 ms FP64, 1280 -> 95.6,
-    # 1472 -> 72.8, 1536 -> 75.2 (FP32 62.6), 1664 -> 91.0, none -> 148.0
+    # 64 Wishart members n ~ U{256..2048}, FP64, graph replay: 1280 -> 88.7 ms,
+    # 1408 -> 81.3, 1472 -> 67.9, 1536 -> 68.0, 1600 -> 68.2, 1728 -> 88.5;
+    # every member batched: 148 (measured with an older batched kernel)
     BLOCKED_MIN_N = 1536
 
     def __init__(self, mats, b: int = -1, update="native",
