@@ -43,7 +43,9 @@ def to_dev(mats, dtype):
             for m in mats]
 
 
-@pytest.mark.parametrize("b", [-1, 16, 64])
+# b = 100 and 128: panels of more than four 16-column blocks (the solve's
+# wide form), 100 with a partial last block
+@pytest.mark.parametrize("b", [-1, 16, 64, 100, 128])
 def test_batched_f64_mixed_sizes(b):
     rng = np.random.default_rng(11)
     sizes = [1, 2, 3, 17, 64, 65, 100, 129, 200, 257, 300, 511] + \
@@ -53,6 +55,17 @@ def test_batched_f64_mixed_sizes(b):
     got = mc.logdet_batched(to_dev(mats, torch.float64), b=b)
     for g, m in zip(got, mats):
         check(g, O.slogdet(m), 1e-9)
+
+
+@pytest.mark.parametrize("b", [100, 128])
+def test_batched_f32_wide_panels(b):
+    g = synth.rng(23)
+    sizes = [int(n) for n in g.integers(100, 600, 10)] + [129, 257]
+    mats = [synth.wishart_from(g, n).astype(np.float32) for n in sizes]
+    print(f"[batched] f32 b={b} sizes={sizes}", flush=True)
+    got = mc.logdet_batched(to_dev(mats, torch.float32), b=b)
+    for gg, m in zip(got, mats):
+        check(gg, O.slogdet(m), 1e-5)
 
 
 @pytest.mark.parametrize("update", ["native", "f32", "bf16x3"])
